@@ -1,0 +1,183 @@
+/*
+ * pmp.h -- exact z-normalized pan-matrix-profile motif search on MI355X.
+ *
+ * C ABI of libpmp (HIP, gfx950).  Every entry point returns 0 on success or a
+ * negative PMP_E* code; no C++ exception crosses this boundary, and
+ * pmp_last_error() returns a thread-local text for the last failure.
+ *
+ * The problem (paper Sec. 2, "Background and Problem"): for a series
+ * T = (t_0 .. t_{n-1}) and every window length m of an interval, the matrix
+ * profile row P_m[i] = min over valid j (|i-j| >= exclusion) of the
+ * z-normalized Euclidean distance d_m(i,j); the top-k pan-motifs are the cells
+ * sorted by distance, skipping any cell within m/2 of an already accepted cell
+ * of the same length.  Constant windows (sigma = 0) are ignored.
+ *
+ * The library runs the paper's one-pass method (Sec. 3: normalized spectral
+ * features, SimHash keys in occupancy-controlled buckets, Parseval-bound
+ * pruning, exact verification) to get a sound upper profile, then certifies
+ * the top-k with an exact threshold join whose completeness follows from the
+ * Parseval bound (Lemma 2), so the reported motifs equal the brute-force
+ * definition:
+ *   - ties between cells are ordered by (distance, m, i);
+ *   - "within m/2" is inclusive (2|i - i'| <= m);
+ *   - distances below 1e-6 are reported as exactly 0 (Sec. 3.6), before ties;
+ *   - j is the smallest minimizer;
+ *   - a window is constant iff its m samples compare equal.
+ */
+#ifndef PMP_H
+#define PMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMP_OK          0
+#define PMP_EINVAL     -1   /* bad argument or non-finite sample            */
+#define PMP_ENOMEM     -2   /* device or host allocation failed / too small */
+#define PMP_EDEVICE    -3   /* HIP runtime error                            */
+#define PMP_EBUSY      -4   /* request still running (pmp_poll)             */
+#define PMP_ENOTFOUND  -5   /* unknown request id                           */
+#define PMP_EINTERNAL  -6   /* internal consistency check failed            */
+
+/* One reported pan-motif: cell (m, i) and its nearest neighbour j, at the
+ * exact z-normalized distance dist (FP64).  32 bytes. */
+typedef struct {
+    int64_t i;
+    int64_t j;
+    int32_t m;
+    int32_t flags;      /* reserved, 0 */
+    double  dist;
+} pmp_motif;
+
+/* Precision of the cached spectral features (Sec. 3.2 "Features are cached in
+ * single precision").  Exact distances are always computed in FP64. */
+enum {
+    PMP_PREC_FP64 = 0,  /* plain form: FP64 features, FP64 bound            */
+    PMP_PREC_FP32 = 1,  /* FP32 features, bound shrunk by a derived margin  */
+    PMP_PREC_BF16 = 2   /* FP32 features for the bound, BF16 MFMA keys      */
+};
+
+typedef struct {
+    uint32_t size;            /* sizeof(pmp_options)                          */
+    int32_t  m_step;          /* lengths m_min, m_min+m_step, ..., <= m_max   */
+    int32_t  precision;       /* PMP_PREC_*                                   */
+    int32_t  spectral_width;  /* K in [2,16]; 0 = calibrate (Sec. 3.2)        */
+    uint64_t seed;            /* seed of the Gaussian projections (Sec. 3.4)  */
+    int32_t  certify;         /* 1: exact top-k (default); 0: top-k of the
+                                 one-pass upper profile, no certificate       */
+    int32_t  signature_bits;  /* B in [1,24], default 24 (Sec. 4)             */
+    int32_t  gamma;           /* R = gamma * budget, default 8 (Sec. 3.4)     */
+    int32_t  probe_ref_depth; /* d0, default 12 (Sec. 3.4)                    */
+    int32_t  probe_cap;       /* cap on Hamming-1 probes, default 8           */
+    int32_t  reserved;
+} pmp_options;
+
+/* Fill *opt with the paper's defaults (Sec. 4 constants). */
+void pmp_default_options(pmp_options *opt);
+
+/* Per-call counters and phase times (all optional reading). */
+typedef struct {
+    uint32_t size;              /* sizeof(pmp_stats)                          */
+    int32_t  K;                 /* spectral width used                        */
+    int32_t  lengths;           /* number of window lengths                   */
+    int32_t  certify_rounds;    /* threshold-join rounds (0 if not certified) */
+    uint64_t cells;             /* sum over m of n - m + 1                    */
+    uint64_t indexed_cells;     /* non-constant windows put in the buckets    */
+    uint64_t pass_candidates;   /* candidate inspections of the one pass      */
+    uint64_t pass_verified;     /* exact distances of the one pass            */
+    uint64_t join_candidates;   /* pairs inside the join bands                */
+    uint64_t join_verified;     /* exact distances of the join                */
+    uint64_t hot_buckets;       /* buckets holding more than R entries        */
+    int32_t  max_depth;         /* deepest directory (bits)                   */
+    int32_t  reserved;
+    double   threshold;         /* final certified threshold T                */
+    double   ms_total;          /* device time of the whole call              */
+    double   ms_onepass;        /* moments + sketch + buckets + probe         */
+    double   ms_certify;        /* selection + threshold join + exact rows    */
+    double   ms_sketch;
+    double   ms_sort;
+    double   ms_probe;
+    double   ms_join;
+    double   ms_rows;
+    uint64_t workspace_bytes;   /* device bytes used by the call              */
+} pmp_stats;
+
+/* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),
+ * valid pairs |i-j| >= exclusion, occupancy target budget (alpha, the paper's
+ * only user knob).  out: caller-owned, capacity k; *n_out = number written
+ * (< k when fewer finite cells exist).  The series is copied before return.
+ * Errors: PMP_EINVAL unless 3 <= m_min <= m_max <= n, k >= 1, exclusion >= 1,
+ * budget >= 1 and every sample is finite. */
+int pmp_open(const double *series, int64_t n, int32_t m_min, int32_t m_max,
+             int32_t k, int32_t exclusion, int32_t budget,
+             pmp_motif *out, int32_t *n_out);
+
+/* Same, with options (NULL = defaults) and optional stats (NULL = none). */
+int pmp_open_ex(const double *series, int64_t n, int32_t m_min, int32_t m_max,
+                int32_t k, int32_t exclusion, int32_t budget,
+                const pmp_options *opt, pmp_motif *out, int32_t *n_out,
+                pmp_stats *stats);
+
+/* Upper bound of the device workspace pmp_run_device needs. */
+size_t pmp_workspace_bytes(int64_t n, int32_t m_min, int32_t m_max,
+                           const pmp_options *opt);
+
+/* Device-resident form: d_series is a device pointer (FP64, n samples) on the
+ * current HIP device; d_workspace/ws_bytes a caller-owned device buffer of at
+ * least pmp_workspace_bytes() bytes (256-byte aligned); stream a hipStream_t
+ * (NULL = default stream).  All work is enqueued on that stream; the call
+ * returns after the results are in `out` (host memory).  The library
+ * allocates no device memory in this form. */
+int pmp_run_device(const double *d_series, int64_t n, int32_t m_min,
+                   int32_t m_max, int32_t k, int32_t exclusion, int32_t budget,
+                   const pmp_options *opt, void *d_workspace, size_t ws_bytes,
+                   void *stream, pmp_motif *out, int32_t *n_out,
+                   pmp_stats *stats);
+
+/* ------------------------------------------------------------- serving */
+
+typedef struct pmp_server pmp_server;
+
+typedef struct {
+    double submit_s;     /* host clock at pmp_submit (CLOCK_MONOTONIC, s) */
+    double start_s;      /* admitted and first work enqueued              */
+    double end_s;        /* results in host memory                        */
+    uint64_t cells;
+    uint64_t workspace_bytes;
+} pmp_timing;
+
+/* A request server on `device` that admits requests while their workspace
+ * fits in hbm_budget_bytes and a slot (HIP stream) is free; admitted requests
+ * run concurrently, each on its own stream.  Thread-safe.  NULL on error. */
+pmp_server *pmp_server_create(int device, size_t hbm_budget_bytes,
+                              int32_t max_slots);
+
+/* Queue a request; the series is copied before return.  *req_id receives its
+ * id.  PMP_EINVAL on bad arguments, PMP_ENOMEM if the request alone can never
+ * fit the HBM budget. */
+int pmp_submit(pmp_server *srv, const double *series, int64_t n,
+               int32_t m_min, int32_t m_max, int32_t k, int32_t exclusion,
+               int32_t budget, const pmp_options *opt, uint64_t *req_id);
+
+/* PMP_EBUSY while pending; on completion copies the motifs (capacity k) and
+ * timing and forgets the request.  Returns the request's own status. */
+int pmp_poll(pmp_server *srv, uint64_t req_id, pmp_motif *out, int32_t *n_out,
+             pmp_timing *timing);
+
+/* Blocks until the request completes, then behaves as pmp_poll. */
+int pmp_wait(pmp_server *srv, uint64_t req_id, pmp_motif *out, int32_t *n_out,
+             pmp_timing *timing);
+
+/* Waits for every admitted request and frees the server. */
+void pmp_server_destroy(pmp_server *srv);
+
+/* Text of the last error on this thread ("" if none). */
+const char *pmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMP_H */

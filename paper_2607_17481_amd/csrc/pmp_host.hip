@@ -1,0 +1,1046 @@
+// pmp_host.hip -- orchestration of the hot path and the C ABI of libpmp.
+//
+// One request runs, on one HIP stream:
+//   change points -> per-length index counts -> depths            (host sync)
+//   pass A: moments + features + SimHash keys      (k_sketch<0>)
+//   ordered compaction + stable radix sort into buckets
+//   pass B: features in bucket order + join records (k_sketch<1>)
+//   probe / Parseval prune / exact verification     (k_probe)      -> upper profile
+//   top-k selection (radix select + greedy)                        (host sync)
+//   certificate: threshold join at T, repeated while needed         (k_join)
+//   exact rows of the reported cells (nearest neighbour)           (k_rows)
+#include "pmp_dev.h"
+#include "pmp.h"
+#include "pmp_stages.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace pmp {
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            return fail(PMP_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_));       \
+    } while (0)
+
+// ------------------------------------------------------------ options
+
+struct Opt {
+    int m_step = 1;
+    int precision = PMP_PREC_FP64;
+    int K = 0;
+    uint64_t seed = 0x5eed2607u;
+    int certify = 1;
+    int B = 24;
+    int gamma = 8;
+    int d0 = 12;
+    int probe_cap = 8;
+};
+
+static int read_options(const pmp_options *o, Opt &out) {
+    Opt d;
+    if (o) {
+        if (o->size != sizeof(pmp_options))
+            return fail(PMP_EINVAL, "pmp_options.size mismatch (%u != %zu)", o->size,
+                        sizeof(pmp_options));
+        d.m_step = o->m_step;
+        d.precision = o->precision;
+        d.K = o->spectral_width;
+        d.seed = o->seed;
+        d.certify = o->certify;
+        d.B = o->signature_bits;
+        d.gamma = o->gamma;
+        d.d0 = o->probe_ref_depth;
+        d.probe_cap = o->probe_cap;
+    }
+    if (d.m_step < 1) return fail(PMP_EINVAL, "m_step must be >= 1");
+    if (d.precision < 0 || d.precision > 2) return fail(PMP_EINVAL, "unknown precision");
+    if (d.K != 0 && (d.K < 2 || d.K > kMaxK)) return fail(PMP_EINVAL, "spectral_width in [2,16] or 0");
+    if (d.B < 1 || d.B > kMaxBits) return fail(PMP_EINVAL, "signature_bits in [1,24]");
+    if (d.gamma < 1) return fail(PMP_EINVAL, "gamma must be >= 1");
+    if (d.d0 < 0) return fail(PMP_EINVAL, "probe_ref_depth must be >= 0");
+    if (d.probe_cap < 0 || d.probe_cap > kProbeSlots) return fail(PMP_EINVAL, "probe_cap in [0,8]");
+    if (d.certify != 0 && d.certify != 1) return fail(PMP_EINVAL, "certify is 0 or 1");
+    out = d;
+    return PMP_OK;
+}
+
+// ------------------------------------------- seeded Gaussian projections
+
+// SplitMix64 output function (Steele, Lea, Flood 2014) used as a
+// counter-based generator: the c-th value of stream `seed`.
+static uint64_t splitmix(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Standard normal by the Box-Muller transform of two counter values.
+static double gauss(uint64_t seed, int m, int l, int c) {
+    const uint64_t ctr = (((uint64_t)m * 64u + (uint64_t)l) * 64u + (uint64_t)c) * 2u;
+    const uint64_t a = splitmix(seed, ctr), b = splitmix(seed, ctr + 1);
+    const double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(b >> 11) * 0x1.0p-53;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586476925286766559 * u2);
+}
+
+constexpr int kFD = 2 * (kMaxK - 1);   // 30 feature reals
+
+// Orthonormal join directions: Gaussian vectors of a stream no length uses
+// (m = 0), made orthonormal by two rounds of modified Gram-Schmidt in FP64.
+static void join_directions(uint64_t seed, double *u /* [kJoinDims][kFD] */) {
+    for (int d = 0; d < kJoinDims; ++d)
+        for (int c = 0; c < kFD; ++c) u[d * kFD + c] = gauss(seed, 0, 32 + d, c);
+    for (int round = 0; round < 2; ++round)
+        for (int d = 0; d < kJoinDims; ++d) {
+            double *v = u + d * kFD;
+            for (int e = 0; e < d; ++e) {
+                const double *w = u + e * kFD;
+                double dot = 0.0;
+                for (int c = 0; c < kFD; ++c) dot += v[c] * w[c];
+                for (int c = 0; c < kFD; ++c) v[c] -= dot * w[c];
+            }
+            double nn = 0.0;
+            for (int c = 0; c < kFD; ++c) nn += v[c] * v[c];
+            nn = std::sqrt(nn);
+            for (int c = 0; c < kFD; ++c) v[c] /= nn;
+        }
+}
+
+static int kprime_of(int K, int m) {
+    int half = (m + 1) / 2 - 1;
+    int kp = std::min(K - 1, half);
+    return kp < 0 ? 0 : kp;
+}
+
+// ----------------------------------------------- spectral width (Sec. 3.2)
+
+// Smallest K in [4, 16] whose retained bins hold a fraction eta of the
+// normalized spectral energy on average, and whose expected accidental
+// collision count n E[(1 - theta_K / pi)^B] stays within 2 gamma alpha, at
+// each of the sampled lengths.  Near-duplicate pairs (angle below 1e-3 rad at
+// the full width) are left out of the collision estimate.
+static int calibrate(const std::vector<std::vector<std::vector<double>>> &sets,
+                     const std::vector<int> &ms, int64_t n, int alpha, int gamma, int B) {
+    const double eta = 0.85;
+    struct W { std::vector<double> re, im; };
+    std::vector<std::vector<W>> spec(sets.size());
+    for (size_t s = 0; s < sets.size(); ++s) {
+        const int m = ms[s];
+        for (const auto &w : sets[s]) {
+            double mu = 0.0;
+            for (double x : w) mu += x;
+            mu /= m;
+            double q = 0.0;
+            for (double x : w) q += (x - mu) * (x - mu);
+            const double sg = std::sqrt(q / m);
+            if (!(sg > 0.0)) continue;
+            W f;
+            f.re.assign(kMaxK, 0.0);
+            f.im.assign(kMaxK, 0.0);
+            const int kp = kprime_of(kMaxK, m);
+            for (int k = 1; k <= kp; ++k) {
+                double re = 0.0, im = 0.0;
+                for (int r = 0; r < m; ++r) {
+                    const double z = (w[r] - mu) / sg;
+                    const double ang = 6.283185307179586 * (double)((int64_t)k * r % m) / m;
+                    re += z * std::cos(ang);
+                    im -= z * std::sin(ang);
+                }
+                f.re[k] = re;
+                f.im[k] = im;
+            }
+            spec[s].push_back(std::move(f));
+        }
+    }
+    for (int K = 4; K <= kMaxK; ++K) {
+        bool ok = true;
+        for (size_t s = 0; s < sets.size() && ok; ++s) {
+            const int m = ms[s];
+            const int kp = kprime_of(K, m), kpf = kprime_of(kMaxK, m);
+            const auto &v = spec[s];
+            if (v.empty()) continue;
+            double e = 0.0;
+            for (const auto &f : v) {
+                double a = 0.0;
+                for (int k = 1; k <= kp; ++k) a += f.re[k] * f.re[k] + f.im[k] * f.im[k];
+                e += 2.0 * a / ((double)m * m);
+            }
+            e /= (double)v.size();
+            if (e < eta) { ok = false; break; }
+            double coll = 0.0;
+            int pairs = 0;
+            for (size_t w = 0; w + 1 < v.size(); ++w) {
+                auto angle = [&](int kk) {
+                    double ab = 0.0, aa = 0.0, bb = 0.0;
+                    for (int k = 1; k <= kk; ++k) {
+                        ab += v[w].re[k] * v[w + 1].re[k] + v[w].im[k] * v[w + 1].im[k];
+                        aa += v[w].re[k] * v[w].re[k] + v[w].im[k] * v[w].im[k];
+                        bb += v[w + 1].re[k] * v[w + 1].re[k] + v[w + 1].im[k] * v[w + 1].im[k];
+                    }
+                    if (!(aa > 0.0 && bb > 0.0)) return 0.0;
+                    double c = ab / std::sqrt(aa * bb);
+                    c = std::max(-1.0, std::min(1.0, c));
+                    return std::acos(c);
+                };
+                if (angle(kpf) < 1e-3) continue;
+                coll += std::pow(1.0 - angle(kp) / M_PI, (double)B);
+                ++pairs;
+            }
+            if (pairs && (double)n * coll / pairs > 2.0 * gamma * alpha) ok = false;
+        }
+        if (ok) return K;
+    }
+    return kMaxK;
+}
+
+static std::vector<int64_t> sample_starts(int64_t W) {
+    std::vector<int64_t> v;
+    if (W <= 256) {
+        for (int64_t i = 0; i < W; ++i) v.push_back(i);
+    } else {
+        for (int j = 0; j < 256; ++j) v.push_back((int64_t)((double)j * (double)(W - 1) / 255.0));
+    }
+    return v;
+}
+
+__global__ void k_gather_windows(const double *__restrict__ t, const int64_t *__restrict__ starts,
+                                 int count, int m, double *__restrict__ out) {
+    const int w = blockIdx.x;
+    if (w >= count) return;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) out[(int64_t)w * m + r] = t[starts[w] + r];
+}
+
+// ------------------------------------------------------------ workspace
+
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, off = 0;
+    bool sizing = false;              // only count bytes
+    std::vector<void *> owned;        // blocks this arena allocated
+    bool can_alloc = false;
+
+    void *take(size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        void *p = sizing ? nullptr : base + off;
+        off += bytes;
+        if (!sizing && off > cap) return nullptr;
+        return sizing ? (void *)1 : p;
+    }
+    ~Arena() {
+        for (void *p : owned) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+static T *take(Arena &a, int64_t count) {
+    return (T *)a.take((size_t)std::max<int64_t>(count, 1) * sizeof(T));
+}
+
+// --------------------------------------------------------------- plan
+
+struct Plan {
+    int64_t n = 0;
+    int L = 0;
+    std::vector<int> ms;
+    std::vector<LenInfo> len;
+    int64_t cells = 0, ntiles = 0, nbuckets = 0, N = 0;
+    int max_m = 0, len_bits = 0, key_shift = 0, jkey_shift = 0, max_depth = 0;
+};
+
+static void plan_lengths(Plan &p, int64_t n, int m_min, int m_max, int step) {
+    p.n = n;
+    p.ms.clear();
+    for (int64_t m = m_min; m <= m_max; m += step) p.ms.push_back((int)m);
+    p.L = (int)p.ms.size();
+    p.len.assign(p.L, LenInfo{});
+    int64_t cb = 0, tb = 0;
+    for (int l = 0; l < p.L; ++l) {
+        LenInfo &L = p.len[l];
+        L.m = p.ms[l];
+        L.W = n - L.m + 1;
+        L.cell_base = cb;
+        L.tile_base = tb;
+        cb += L.W;
+        tb += (L.W + kTileW - 1) / kTileW;
+    }
+    p.cells = cb;
+    p.ntiles = tb;
+    p.max_m = p.ms.back();
+    p.len_bits = 0;
+    while ((1 << p.len_bits) < p.L) ++p.len_bits;
+}
+
+// depths, probes, bases from the index counts
+static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, int alpha) {
+    const int dcap = std::min(o.B, 32 - p.len_bits - 1);
+    int64_t sb = 0, bb = 0;
+    p.max_depth = 0;
+    for (int l = 0; l < p.L; ++l) {
+        LenInfo &L = p.len[l];
+        L.kprime = 0;
+        L.n_index = cnt[l];
+        int d = 0;
+        while (d < dcap && L.n_index > (int64_t)alpha << d) ++d;   // Prop. 4 final depth
+        L.depth = d;
+        int h = d > 0 ? 1 + std::max(0, d - o.d0) : 0;
+        h = std::min(h, std::min(d, o.probe_cap));
+        L.probes = h;
+        L.slot_base = sb;
+        L.bucket_base = bb;
+        sb += L.n_index;
+        bb += (int64_t)1 << d;
+        p.max_depth = std::max(p.max_depth, d);
+    }
+    p.N = sb;
+    p.nbuckets = bb;
+    p.key_shift = p.max_depth;
+    p.jkey_shift = 32 - p.len_bits - 1;
+}
+
+struct Bufs {
+    // phase 1
+    LenInfo *len;
+    uint32_t *flags, *E, *scan_tmp;
+    int *bad;
+    unsigned long long *counts, *counters;
+    float *emax, *gproj;
+    double *ujoin;
+    unsigned int *hist;
+    uint32_t *nless;
+    double *mu, *isig;
+    uint64_t *P, *keyw_nat;
+    uint32_t *tile_cnt, *inv;
+    uint32_t *sel_cnt;
+    uint32_t *less_cell, *eq;
+    uint64_t *less_val;
+    RowReq *rows;
+    unsigned long long *row_min, *row_arg;
+    int64_t *cal_starts;
+    double *cal_win;
+    // phase 2
+    uint32_t *skey, *sval, *skey2, *sval2;
+    void *sort_tmp;
+    uint32_t *bstart;
+    void *F;
+    uint64_t *keyw;
+    float *jrec, *jsorted, *prange;
+    uint32_t *jk, *jv, *jk2, *jv2;
+    JoinLen *jl;
+};
+
+static int64_t need_select(int k, int m_max) { return (int64_t)k * (m_max + 1); }
+
+static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
+    const int64_t nsel = select_blocks(p.cells) + 1;
+    const int64_t need = need_select(k, p.max_m);
+    b.len = take<LenInfo>(a, p.L);
+    b.flags = take<uint32_t>(a, p.n + 1);
+    b.E = take<uint32_t>(a, p.n + 1);
+    b.scan_tmp = (uint32_t *)a.take(scan_temp_bytes(std::max<int64_t>(
+        {p.n + 1, p.ntiles + 1, p.cells, nsel, (int64_t)1 << 26})));
+    b.bad = take<int>(a, 1);
+    b.counts = take<unsigned long long>(a, p.L);
+    b.counters = take<unsigned long long>(a, C_NCOUNTERS);
+    b.emax = take<float>(a, p.L);
+    b.gproj = take<float>(a, (int64_t)p.L * kMaxBits * kFD);
+    b.ujoin = take<double>(a, kJoinDims * kFD);
+    b.hist = take<unsigned int>(a, 2048);
+    b.nless = take<uint32_t>(a, 1);
+    b.mu = take<double>(a, p.cells);
+    b.isig = take<double>(a, p.cells);
+    b.P = take<uint64_t>(a, p.cells);
+    b.keyw_nat = take<uint64_t>(a, p.cells);
+    b.tile_cnt = take<uint32_t>(a, p.ntiles + 1);
+    b.inv = take<uint32_t>(a, p.cells);
+    b.sel_cnt = take<uint32_t>(a, nsel);
+    b.less_cell = take<uint32_t>(a, need);
+    b.less_val = take<uint64_t>(a, need);
+    b.eq = take<uint32_t>(a, need);
+    b.rows = take<RowReq>(a, k);
+    b.row_min = take<unsigned long long>(a, k);
+    b.row_arg = take<unsigned long long>(a, k);
+    b.cal_starts = take<int64_t>(a, 3 * 256);
+    b.cal_win = take<double>(a, (int64_t)3 * 256 * p.max_m);
+}
+
+static void carve2(Arena &a, Bufs &b, const Plan &p, int precision) {
+    const int64_t N = p.N;
+    b.skey = take<uint32_t>(a, N);
+    b.sval = take<uint32_t>(a, N);
+    b.skey2 = take<uint32_t>(a, N);
+    b.sval2 = take<uint32_t>(a, N);
+    b.sort_tmp = a.take(sort_temp_bytes(std::max<int64_t>(N, 1)));
+    b.bstart = take<uint32_t>(a, p.nbuckets + 1);
+    b.F = a.take((size_t)std::max<int64_t>(N, 1) * kRec * (precision == 0 ? 8 : 4));
+    b.keyw = take<uint64_t>(a, N);
+    b.jrec = take<float>(a, N * 8);
+    b.jsorted = take<float>(a, N * 8);
+    b.jk = take<uint32_t>(a, N);
+    b.jv = take<uint32_t>(a, N);
+    b.jk2 = take<uint32_t>(a, N);
+    b.jv2 = take<uint32_t>(a, N);
+    b.prange = take<float>(a, p.L);
+    b.jl = take<JoinLen>(a, p.L);
+}
+
+// ------------------------------------------------------------ selection
+
+struct Cand {
+    double d;
+    int l;
+    int64_t i;
+};
+
+static bool cand_less(const Cand &a, const Cand &b, const Plan &p) {
+    if (a.d != b.d) return a.d < b.d;
+    if (p.ms[a.l] != p.ms[b.l]) return p.ms[a.l] < p.ms[b.l];
+    return a.i < b.i;
+}
+
+static int len_of_cell(const Plan &p, int64_t cell) {
+    int lo = 0, hi = p.L - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (p.len[mid].cell_base <= cell) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The first `need` cells of the (P, m, i) order, sorted, then the greedy of
+// Sec. 2 over them.  Returns the accepted cells.
+static int select_topk(const Plan &p, Bufs &b, const uint64_t *dP, int k, hipStream_t s,
+                       std::vector<Cand> &accepted) {
+    accepted.clear();
+    const int64_t need_all = need_select(k, p.max_m);
+    const int shifts[6] = {53, 42, 31, 20, 9, 0};
+    const int widths[6] = {11, 11, 11, 11, 11, 9};
+    uint64_t high = 0;
+    int64_t remaining = need_all;
+    uint64_t pivot = kInfBits;
+    int64_t need_eq = 0;
+    std::vector<unsigned int> h(2048);
+    for (int ps = 0; ps < 6; ++ps) {
+        HIPCHK(hipMemsetAsync(b.hist, 0, 2048 * sizeof(unsigned int), s));
+        launch_select_hist(dP, p.cells, shifts[ps], widths[ps], high, b.hist, s);
+        HIPCHK(hipMemcpyAsync(h.data(), b.hist, (1 << widths[ps]) * sizeof(unsigned int),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int64_t tot = 0;
+        for (int i = 0; i < (1 << widths[ps]); ++i) tot += h[i];
+        if (ps == 0 && tot < remaining) {   // fewer finite cells than needed: take all
+            pivot = kInfBits;
+            need_eq = 0;
+            break;
+        }
+        int64_t cum = 0;
+        int bin = -1;
+        for (int i = 0; i < (1 << widths[ps]); ++i) {
+            if (cum + h[i] >= remaining) { bin = i; break; }
+            cum += h[i];
+        }
+        remaining -= cum;
+        high = (high << widths[ps]) | (uint64_t)bin;
+        if (ps == 0 && bin == 0) {           // exponent field 0: only exact zeros
+            pivot = 0;
+            need_eq = remaining;
+            break;
+        }
+        if (ps == 5) {
+            pivot = high;
+            need_eq = remaining;
+        }
+    }
+    // ordered compaction
+    const int64_t nsb = select_blocks(p.cells);
+    launch_select_count(dP, p.cells, pivot, b.sel_cnt, s);
+    scan_exclusive_u32(b.sel_cnt, b.sel_cnt, nsb, nullptr, b.scan_tmp, s);
+    HIPCHK(hipMemsetAsync(b.nless, 0, sizeof(uint32_t), s));
+    launch_select_emit(dP, p.cells, pivot, (uint32_t)need_eq, b.sel_cnt, b.less_cell, b.less_val,
+                       b.nless, (uint32_t)need_all, b.eq, s);
+    uint32_t nless = 0;
+    HIPCHK(hipMemcpyAsync(&nless, b.nless, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nless > (uint32_t)need_all) return fail(PMP_EINTERNAL, "selection overflow");
+    std::vector<uint32_t> lc(nless), ec(need_eq);
+    if (nless)
+        HIPCHK(hipMemcpyAsync(lc.data(), b.less_cell, nless * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, s));
+    if (need_eq)
+        HIPCHK(hipMemcpyAsync(ec.data(), b.eq, need_eq * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    std::vector<uint64_t> lv(nless);
+    if (nless)
+        HIPCHK(hipMemcpyAsync(lv.data(), b.less_val, nless * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<Cand> c;
+    c.reserve(nless + need_eq);
+    for (uint32_t x = 0; x < nless; ++x) {
+        double d;
+        memcpy(&d, &lv[x], 8);
+        int l = len_of_cell(p, lc[x]);
+        c.push_back({d, l, (int64_t)lc[x] - p.len[l].cell_base});
+    }
+    std::sort(c.begin(), c.end(), [&](const Cand &a, const Cand &bb) { return cand_less(a, bb, p); });
+    double pv;
+    memcpy(&pv, &pivot, 8);
+    for (int64_t x = 0; x < need_eq; ++x) {
+        int l = len_of_cell(p, ec[x]);
+        c.push_back({pv, l, (int64_t)ec[x] - p.len[l].cell_base});
+    }
+    // greedy (Sec. 2): skip a cell within m/2 of an accepted cell of its length
+    for (const Cand &x : c) {
+        const int m = p.ms[x.l];
+        bool skip = false;
+        for (const Cand &a : accepted)
+            if (a.l == x.l && 2 * std::llabs(a.i - x.i) <= m) { skip = true; break; }
+        if (skip) continue;
+        accepted.push_back(x);
+        if ((int)accepted.size() == k) break;
+    }
+    return PMP_OK;
+}
+
+// ------------------------------------------------------------- pipeline
+
+struct Timer {
+    hipEvent_t ev[8];
+    bool ok = false;
+    Timer() {
+        ok = true;
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) ok = false;
+    }
+    ~Timer() {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t s) {
+        if (ok) (void)hipEventRecord(ev[i], s);
+    }
+    double ms(int a, int b) {
+        float x = 0.0f;
+        if (ok && hipEventElapsedTime(&x, ev[a], ev[b]) == hipSuccess) return x;
+        return 0.0;
+    }
+};
+
+static int check_args(int64_t n, int m_min, int m_max, int k, int excl, int budget) {
+    if (n < 3) return fail(PMP_EINVAL, "series must have at least 3 samples");
+    if (!(3 <= m_min && m_min <= m_max && (int64_t)m_max <= n))
+        return fail(PMP_EINVAL, "need 3 <= m_min <= m_max <= n");
+    if (m_max > kMaxM) return fail(PMP_EINVAL, "window lengths above %d are not supported", kMaxM);
+    if (k < 1) return fail(PMP_EINVAL, "k must be >= 1");
+    if (excl < 1) return fail(PMP_EINVAL, "exclusion must be >= 1");
+    if (budget < 1) return fail(PMP_EINVAL, "budget must be >= 1");
+    return PMP_OK;
+}
+
+static size_t upper_bytes(int64_t n, int m_min, int m_max, const Opt &o, int k) {
+    Plan p;
+    plan_lengths(p, n, m_min, m_max, o.m_step);
+    std::vector<int64_t> cnt(p.L);
+    for (int l = 0; l < p.L; ++l) cnt[l] = p.len[l].W;
+    plan_index(p, cnt, o, 1);     // alpha = 1 gives the deepest directories
+    Arena a;
+    a.sizing = true;
+    Bufs b;
+    carve1(a, b, p, k);
+    carve2(a, b, p, o.precision);
+    return a.off + 4096;
+}
+
+struct Run {
+    const double *t;
+    int64_t n;
+    int m_min, m_max, k, excl, budget;
+    Opt o;
+    hipStream_t s;
+    pmp_motif *out;
+    int32_t *n_out;
+    pmp_stats *st;
+    pmp_debug *dbg;
+};
+
+__global__ void k_debug_sigma(const double *__restrict__ isig, int64_t n, double *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = isig[i] != 0.0 ? 1.0 / isig[i] : 0.0;
+}
+
+template <typename FT>
+__global__ void k_debug_features(const FT *__restrict__ F, const uint32_t *__restrict__ inv,
+                                 const double *__restrict__ isig, int64_t cells,
+                                 FT *__restrict__ out) {
+    int64_t c = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
+    int e = threadIdx.x % 32;
+    if (c >= cells) return;
+    out[c * kRec + e] = isig[c] != 0.0 ? F[(int64_t)inv[c] * kRec + e] : (FT)0;
+}
+
+static int run_pipeline(Run &R, Arena &ar) {
+    const hipStream_t s = R.s;
+    const Opt &o = R.o;
+    Plan p;
+    plan_lengths(p, R.n, R.m_min, R.m_max, o.m_step);
+    if (p.cells >= (int64_t)UINT32_MAX - 1) return fail(PMP_EINVAL, "too many cells (%lld)", (long long)p.cells);
+    Bufs b;
+    carve1(ar, b, p, R.k);
+    if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
+    Timer tm;
+    tm.mark(0, s);
+
+    // ---- validation, change points, index counts
+    HIPCHK(hipMemsetAsync(b.bad, 0, sizeof(int), s));
+    launch_changepoints(R.t, R.n, b.flags, b.bad, s);
+    scan_exclusive_u32(b.flags, b.E, R.n + 1, nullptr, b.scan_tmp, s);
+    HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(b.counts, 0, p.L * sizeof(unsigned long long), s));
+    launch_count_index(b.len, p.L, b.E, b.counts, p.len[0].W, s);
+    int bad = 0;
+    std::vector<int64_t> cnt(p.L);
+    HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(cnt.data(), b.counts, p.L * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    // calibration samples
+    std::vector<int> cal_m;
+    std::vector<std::vector<int64_t>> cal_st;
+    if (o.K == 0) {
+        int idx[3] = {0, (p.L - 1) / 2, p.L - 1};
+        std::vector<int64_t> all;
+        for (int a = 0; a < 3; ++a) {
+            if (a > 0 && idx[a] == idx[a - 1]) continue;
+            cal_m.push_back(p.ms[idx[a]]);
+            cal_st.push_back(sample_starts(p.len[idx[a]].W));
+        }
+        for (size_t a = 0; a < cal_m.size(); ++a) {
+            std::vector<int64_t> st = cal_st[a];
+            HIPCHK(hipMemcpyAsync(b.cal_starts, st.data(), st.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_gather_windows, dim3((unsigned)st.size()), dim3(256), 0, s, R.t,
+                               (const int64_t *)b.cal_starts, (int)st.size(), cal_m[a],
+                               b.cal_win + (int64_t)a * 256 * p.max_m);
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(PMP_EINVAL, "series contains a non-finite sample");
+    int K = o.K;
+    if (K == 0) {
+        std::vector<std::vector<std::vector<double>>> sets(cal_m.size());
+        std::vector<double> host((size_t)3 * 256 * p.max_m);
+        HIPCHK(hipMemcpy(host.data(), b.cal_win, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t a = 0; a < cal_m.size(); ++a)
+            for (size_t w = 0; w < cal_st[a].size(); ++w) {
+                const double *src = host.data() + (a * 256 + w) * p.max_m;
+                sets[a].emplace_back(src, src + cal_m[a]);
+            }
+        K = calibrate(sets, cal_m, R.n, R.budget, o.gamma, o.B);
+    }
+    plan_index(p, cnt, o, R.budget);
+    for (int l = 0; l < p.L; ++l) p.len[l].kprime = kprime_of(K, p.ms[l]);
+    if (p.N >= (int64_t)UINT32_MAX - 1) return fail(PMP_EINVAL, "too many windows");
+    carve2(ar, b, p, o.precision);
+    if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
+
+    // ---- per-request constants
+    {
+        std::vector<float> g((size_t)p.L * o.B * kFD);
+        for (int l = 0; l < p.L; ++l)
+            for (int bb = 0; bb < o.B; ++bb)
+                for (int c = 0; c < kFD; ++c)
+                    g[((size_t)l * o.B + bb) * kFD + c] = (float)gauss(o.seed, p.ms[l], bb, c);
+        HIPCHK(hipMemcpyAsync(b.gproj, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        double u[kJoinDims * kFD];
+        join_directions(o.seed, u);
+        HIPCHK(hipMemcpyAsync(b.ujoin, u, sizeof(u), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
+        std::vector<float> pr(p.L);
+        for (int l = 0; l < p.L; ++l) pr[l] = (float)(p.ms[l] / std::sqrt(2.0) * 1.01 + 1.0);
+        HIPCHK(hipMemcpyAsync(b.prange, pr.data(), p.L * sizeof(float), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
+    }
+    launch_fill_u64(b.P, p.cells, kInfBits, s);
+    HIPCHK(hipMemsetAsync(b.emax, 0, p.L * sizeof(float), s));
+    HIPCHK(hipMemsetAsync(b.counters, 0, C_NCOUNTERS * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(b.bstart, 0, (p.nbuckets + 1) * sizeof(uint32_t), s));
+
+    Req q{};
+    q.t = R.t;
+    q.n = R.n;
+    q.L = p.L;
+    q.K = K;
+    q.B = o.B;
+    q.excl = R.excl;
+    q.budget_R = o.gamma * R.budget;
+    q.key_shift = p.key_shift;
+    q.jkey_shift = p.jkey_shift;
+    q.precision = o.precision;
+    q.len = b.len;
+    q.cpre = (const int32_t *)b.E;
+    q.mu = b.mu;
+    q.isig = b.isig;
+    q.P = b.P;
+    q.keyw_nat = b.keyw_nat;
+    q.skey = b.skey;
+    q.sval = b.sval;
+    q.bucket_cnt = b.bstart;
+    q.perm = b.sval;
+    q.inv = b.inv;
+    q.F = b.F;
+    q.keyw = b.keyw;
+    q.gproj = b.gproj;
+    q.ujoin = b.ujoin;
+    q.jrec = b.jrec;
+    q.emax = b.emax;
+    q.counters = b.counters;
+    q.bad = b.bad;
+
+    // ---- pass A, buckets, pass B
+    tm.mark(1, s);
+    launch_sketch(0, o.precision, q, b.E, b.tile_cnt, p.ntiles, p.max_m, s);
+    scan_exclusive_u32(b.tile_cnt, b.tile_cnt, p.ntiles, nullptr, b.scan_tmp, s);
+    launch_emit_sortin(q, b.tile_cnt, p.ntiles, s);
+    tm.mark(2, s);
+    radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, p.N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
+    scan_exclusive_u32(b.bstart, b.bstart, p.nbuckets + 1, nullptr, b.scan_tmp, s);
+    launch_invert(b.sval, p.N, b.inv, s);
+    tm.mark(3, s);
+    launch_sketch(1, o.precision, q, b.E, b.tile_cnt, p.ntiles, p.max_m, s);
+    tm.mark(4, s);
+    launch_probe(o.precision, q, b.bstart, p.N, s);
+    launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
+    tm.mark(5, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
+
+    if (R.dbg && R.dbg->profile_pass)
+        HIPCHK(hipMemcpyAsync(R.dbg->profile_pass, b.P, p.cells * 8, hipMemcpyDeviceToDevice, s));
+
+    // ---- selection on the upper profile
+    std::vector<Cand> acc;
+    int rc = select_topk(p, b, b.P, R.k, s, acc);
+    if (rc) return rc;
+    int rounds = 0;
+    double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
+    if (o.certify) {
+        launch_join_keys(q, b.prange, p.N, b.jk, b.jv, s);
+        radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, p.N, 0, p.jkey_shift + p.len_bits, b.sort_tmp, s);
+        launch_join_gather(b.jrec, b.jv, p.N, b.jsorted, s);
+        std::vector<float> emax(p.L);
+        HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<JoinLen> jl(p.L);
+        for (;;) {
+            ++rounds;
+            const double Teff = std::max(T, kEps0);
+            for (int l = 0; l < p.L; ++l) {
+                const double m = p.ms[l];
+                const double u32 = 5.9604644775390625e-08;
+                const double dp = 2.0 * u32 * (m / std::sqrt(2.0) * 1.01 + 1.0) + 1e-12 * m;
+                if (std::isinf(Teff)) {
+                    jl[l].r_filter = INFINITY;
+                    jl[l].r_key = INFINITY;
+                } else {
+                    const double r = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9) + 2.0 * (double)emax[l];
+                    const double rf = (r + 2.0 * std::sqrt((double)kJoinDims) * dp) * (1.0 + 1e-5) + 1e-30;
+                    jl[l].r_filter = (float)rf * (1.0f + 1e-6f);
+                    jl[l].r_key = (float)(rf * (1.0 + 1e-5) + 1e-6 * (1.0 + m));
+                }
+                jl[l].prange = (float)(m / std::sqrt(2.0) * 1.01 + 1.0);
+                jl[l].pad = 0.0f;
+            }
+            HIPCHK(hipMemcpyAsync(b.jl, jl.data(), p.L * sizeof(JoinLen), hipMemcpyHostToDevice, s));
+            launch_join(o.precision, q, b.jsorted, b.jk, b.jl, p.N, Teff, s);
+            HIPCHK(hipGetLastError());
+            rc = select_topk(p, b, b.P, R.k, s, acc);
+            if (rc) return rc;
+            if (std::isinf(T)) break;                               // exhaustive
+            if (acc.size() == (size_t)R.k && acc.back().d <= T) break;
+            T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
+            if (rounds > 64) return fail(PMP_EINTERNAL, "threshold join did not converge");
+        }
+    }
+    tm.mark(6, s);
+
+    // ---- exact rows of the reported cells
+    const int nacc = (int)acc.size();
+    std::vector<RowReq> rr(nacc);
+    for (int x = 0; x < nacc; ++x) {
+        rr[x].l = acc[x].l;
+        rr[x].pad = 0;
+        rr[x].i = acc[x].i;
+        double d = acc[x].d;
+        memcpy(&rr[x].target, &d, 8);
+    }
+    std::vector<unsigned long long> rmin(nacc), rarg(nacc);
+    if (nacc) {
+        HIPCHK(hipMemcpyAsync(b.rows, rr.data(), nacc * sizeof(RowReq), hipMemcpyHostToDevice, s));
+        launch_fill_u64((uint64_t *)b.row_min, nacc, kInfBits, s);
+        launch_fill_u64((uint64_t *)b.row_arg, nacc, ~0ull, s);
+        if (o.certify) {
+            launch_rows(q, b.rows, nacc, p.len[0].W, 1, b.row_min, b.row_arg, s);
+            HIPCHK(hipMemcpyAsync(rmin.data(), b.row_min, nacc * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int x = 0; x < nacc; ++x)
+                if (rmin[x] != rr[x].target) {
+                    double a, bq;
+                    memcpy(&a, &rmin[x], 8);
+                    memcpy(&bq, &rr[x].target, 8);
+                    return fail(PMP_EINTERNAL,
+                                "certificate mismatch at m=%d i=%lld: row minimum %.17g, "
+                                "certified value %.17g",
+                                p.ms[acc[x].l], (long long)acc[x].i, a, bq);
+                }
+        }
+        launch_rows(q, b.rows, nacc, p.len[0].W, 0, b.row_min, b.row_arg, s);
+        HIPCHK(hipMemcpyAsync(rarg.data(), b.row_arg, nacc * 8, hipMemcpyDeviceToHost, s));
+    }
+    tm.mark(7, s);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    for (int x = 0; x < nacc; ++x) {
+        R.out[x].i = acc[x].i;
+        R.out[x].j = (int64_t)rarg[x];
+        R.out[x].m = p.ms[acc[x].l];
+        R.out[x].flags = 0;
+        R.out[x].dist = acc[x].d;
+    }
+    *R.n_out = nacc;
+
+    if (R.dbg) {
+        pmp_debug *d = R.dbg;
+        d->K = K;
+        for (int l = 0; l < p.L; ++l) {
+            if (d->lengths) d->lengths[l] = p.ms[l];
+            if (d->depth) d->depth[l] = p.len[l].depth;
+            if (d->indexed) d->indexed[l] = p.len[l].n_index;
+        }
+        if (d->mu) HIPCHK(hipMemcpyAsync(d->mu, b.mu, p.cells * 8, hipMemcpyDeviceToDevice, s));
+        if (d->sigma)
+            hipLaunchKernelGGL(k_debug_sigma, dim3((unsigned)((p.cells + 255) / 256)), dim3(256), 0, s,
+                               b.isig, p.cells, d->sigma);
+        if (d->profile_final)
+            HIPCHK(hipMemcpyAsync(d->profile_final, b.P, p.cells * 8, hipMemcpyDeviceToDevice, s));
+        if (d->keys) HIPCHK(hipMemcpyAsync(d->keys, b.keyw_nat, p.cells * 8, hipMemcpyDeviceToDevice, s));
+        if (d->perm) HIPCHK(hipMemcpyAsync(d->perm, b.sval, p.N * 4, hipMemcpyDeviceToDevice, s));
+        if (d->bucket_start)
+            HIPCHK(hipMemcpyAsync(d->bucket_start, b.bstart, (p.nbuckets + 1) * 4,
+                                  hipMemcpyDeviceToDevice, s));
+        if (d->features) {
+            if (o.precision == 0)
+                hipLaunchKernelGGL(k_debug_features<double>, dim3((unsigned)((p.cells + 7) / 8)),
+                                   dim3(256), 0, s, (const double *)b.F, b.inv, b.isig, p.cells,
+                                   (double *)d->features);
+            else
+                hipLaunchKernelGGL(k_debug_features<float>, dim3((unsigned)((p.cells + 7) / 8)),
+                                   dim3(256), 0, s, (const float *)b.F, b.inv, b.isig, p.cells,
+                                   (float *)d->features);
+        }
+        HIPCHK(hipStreamSynchronize(s));
+    }
+
+    if (R.st) {
+        pmp_stats *st = R.st;
+        std::vector<unsigned long long> ctr(C_NCOUNTERS);
+        HIPCHK(hipMemcpy(ctr.data(), b.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost));
+        st->K = K;
+        st->lengths = p.L;
+        st->certify_rounds = rounds;
+        st->cells = (uint64_t)p.cells;
+        st->indexed_cells = (uint64_t)p.N;
+        st->pass_candidates = ctr[C_PASS_CAND];
+        st->pass_verified = ctr[C_PASS_VER];
+        st->join_candidates = ctr[C_JOIN_CAND];
+        st->join_verified = ctr[C_JOIN_VER];
+        st->hot_buckets = ctr[C_HOT];
+        st->max_depth = p.max_depth;
+        st->threshold = T;
+        st->ms_total = tm.ms(0, 7);
+        st->ms_onepass = tm.ms(0, 5);
+        st->ms_certify = tm.ms(5, 7);
+        st->ms_sketch = tm.ms(1, 2) + tm.ms(3, 4);
+        st->ms_sort = tm.ms(2, 3);
+        st->ms_probe = tm.ms(4, 5);
+        st->ms_join = tm.ms(5, 6);
+        st->ms_rows = tm.ms(6, 7);
+        st->workspace_bytes = ar.off;
+    }
+    return PMP_OK;
+}
+
+static int run_device(const double *d_series, int64_t n, int32_t m_min, int32_t m_max, int32_t k,
+                      int32_t excl, int32_t budget, const pmp_options *opt, void *ws,
+                      size_t ws_bytes, void *stream, pmp_motif *out, int32_t *n_out,
+                      pmp_stats *stats, pmp_debug *dbg) {
+    g_err.clear();
+    if (!d_series || !out || !n_out) return fail(PMP_EINVAL, "null argument");
+    if (stats && stats->size != sizeof(pmp_stats)) return fail(PMP_EINVAL, "pmp_stats.size mismatch");
+    if (dbg && dbg->size != sizeof(pmp_debug)) return fail(PMP_EINVAL, "pmp_debug.size mismatch");
+    int rc = check_args(n, m_min, m_max, k, excl, budget);
+    if (rc) return rc;
+    Run R{};
+    rc = read_options(opt, R.o);
+    if (rc) return rc;
+    if (!ws || ((uintptr_t)ws & 255)) return fail(PMP_EINVAL, "workspace must be 256-byte aligned");
+    R.t = d_series;
+    R.n = n;
+    R.m_min = m_min;
+    R.m_max = m_max;
+    R.k = k;
+    R.excl = excl;
+    R.budget = budget;
+    R.s = (hipStream_t)stream;
+    R.out = out;
+    R.n_out = n_out;
+    R.st = stats;
+    R.dbg = dbg;
+    *n_out = 0;
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    try {
+        return run_pipeline(R, ar);
+    } catch (...) {
+        return fail(PMP_EINTERNAL, "unexpected host exception");
+    }
+}
+
+}  // namespace pmp
+
+using namespace pmp;
+
+extern "C" {
+
+void pmp_default_options(pmp_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->size = sizeof(pmp_options);
+    Opt d;
+    o->m_step = d.m_step;
+    o->precision = d.precision;
+    o->spectral_width = d.K;
+    o->seed = d.seed;
+    o->certify = d.certify;
+    o->signature_bits = d.B;
+    o->gamma = d.gamma;
+    o->probe_ref_depth = d.d0;
+    o->probe_cap = d.probe_cap;
+}
+
+const char *pmp_last_error(void) { return g_err.c_str(); }
+
+size_t pmp_workspace_bytes(int64_t n, int32_t m_min, int32_t m_max, const pmp_options *opt) {
+    Opt o;
+    if (read_options(opt, o)) return 0;
+    if (check_args(n, m_min, m_max, 1, 1, 1)) return 0;
+    return upper_bytes(n, m_min, m_max, o, 64);
+}
+
+int pmp_run_device(const double *d_series, int64_t n, int32_t m_min, int32_t m_max, int32_t k,
+                   int32_t exclusion, int32_t budget, const pmp_options *opt, void *d_workspace,
+                   size_t ws_bytes, void *stream, pmp_motif *out, int32_t *n_out,
+                   pmp_stats *stats) {
+    return run_device(d_series, n, m_min, m_max, k, exclusion, budget, opt, d_workspace, ws_bytes,
+                      stream, out, n_out, stats, nullptr);
+}
+
+int pmp_run_device_debug(const double *d_series, int64_t n, int32_t m_min, int32_t m_max,
+                         int32_t k, int32_t exclusion, int32_t budget, const pmp_options *opt,
+                         void *d_workspace, size_t ws_bytes, void *stream, pmp_motif *out,
+                         int32_t *n_out, pmp_stats *stats, pmp_debug *dbg) {
+    return run_device(d_series, n, m_min, m_max, k, exclusion, budget, opt, d_workspace, ws_bytes,
+                      stream, out, n_out, stats, dbg);
+}
+
+int pmp_open_ex(const double *series, int64_t n, int32_t m_min, int32_t m_max, int32_t k,
+                int32_t exclusion, int32_t budget, const pmp_options *opt, pmp_motif *out,
+                int32_t *n_out, pmp_stats *stats) {
+    g_err.clear();
+    if (!series || !out || !n_out) return fail(PMP_EINVAL, "null argument");
+    int rc = check_args(n, m_min, m_max, k, exclusion, budget);
+    if (rc) return rc;
+    Opt o;
+    rc = read_options(opt, o);
+    if (rc) return rc;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(series[i])) return fail(PMP_EINVAL, "series contains a non-finite sample");
+    const size_t ws = upper_bytes(n, m_min, m_max, o, k);
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    double *d_t = nullptr;
+    void *d_ws = nullptr;
+    if (hipMalloc(&d_t, (size_t)n * sizeof(double)) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return fail(PMP_ENOMEM, "device allocation of the series failed");
+    }
+    if (hipMalloc(&d_ws, ws) != hipSuccess) {
+        (void)hipFree(d_t);
+        (void)hipStreamDestroy(s);
+        return fail(PMP_ENOMEM, "device allocation of %zu workspace bytes failed", ws);
+    }
+    rc = PMP_OK;
+    if (hipMemcpyAsync(d_t, series, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = fail(PMP_EDEVICE, "copy of the series failed");
+    if (!rc)
+        rc = run_device(d_t, n, m_min, m_max, k, exclusion, budget, opt, d_ws, ws, (void *)s, out,
+                        n_out, stats, nullptr);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(d_ws);
+    (void)hipFree(d_t);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
+int pmp_open(const double *series, int64_t n, int32_t m_min, int32_t m_max, int32_t k,
+             int32_t exclusion, int32_t budget, pmp_motif *out, int32_t *n_out) {
+    return pmp_open_ex(series, n, m_min, m_max, k, exclusion, budget, nullptr, out, n_out, nullptr);
+}
+
+double pmp_projection(uint64_t seed, int32_t m, int32_t l, int32_t c) { return gauss(seed, m, l, c); }
+
+int pmp_calibrate_width(const double *series, int64_t n, int32_t m_min, int32_t m_max,
+                        int32_t m_step, int32_t budget, int32_t gamma, int32_t bits, int32_t *K) {
+    g_err.clear();
+    if (!series || !K) return fail(PMP_EINVAL, "null argument");
+    int rc = check_args(n, m_min, m_max, 1, 1, budget);
+    if (rc) return rc;
+    if (m_step < 1 || gamma < 1 || bits < 1 || bits > kMaxBits) return fail(PMP_EINVAL, "bad option");
+    Plan p;
+    plan_lengths(p, n, m_min, m_max, m_step);
+    int idx[3] = {0, (p.L - 1) / 2, p.L - 1};
+    std::vector<int> ms;
+    std::vector<std::vector<std::vector<double>>> sets;
+    for (int a = 0; a < 3; ++a) {
+        if (a > 0 && idx[a] == idx[a - 1]) continue;
+        const int m = p.ms[idx[a]];
+        ms.push_back(m);
+        std::vector<std::vector<double>> set;
+        for (int64_t i : sample_starts(n - m + 1)) set.emplace_back(series + i, series + i + m);
+        sets.push_back(std::move(set));
+    }
+    *K = calibrate(sets, ms, n, budget, gamma, bits);
+    return PMP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""ctypes binding of libpmp (argument marshalling only).
+
+Every step of the computation runs in the HIP library; this module only
+converts arguments.  It raises if ``libpmp.so`` is missing: there is no CPU
+fallback.  PyTorch provides device memory and streams for the device-resident
+entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpmp.so")
+
+PMP_OK, PMP_EINVAL, PMP_ENOMEM, PMP_EDEVICE, PMP_EBUSY, PMP_ENOTFOUND, PMP_EINTERNAL = (
+    0, -1, -2, -3, -4, -5, -6)
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+
+
+class MotifC(C.Structure):
+    _fields_ = [("i", C.c_int64), ("j", C.c_int64), ("m", C.c_int32), ("flags", C.c_int32),
+                ("dist", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("m_step", C.c_int32), ("precision", C.c_int32),
+                ("spectral_width", C.c_int32), ("seed", C.c_uint64), ("certify", C.c_int32),
+                ("signature_bits", C.c_int32), ("gamma", C.c_int32),
+                ("probe_ref_depth", C.c_int32), ("probe_cap", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("K", C.c_int32), ("lengths", C.c_int32),
+                ("certify_rounds", C.c_int32), ("cells", C.c_uint64),
+                ("indexed_cells", C.c_uint64), ("pass_candidates", C.c_uint64),
+                ("pass_verified", C.c_uint64), ("join_candidates", C.c_uint64),
+                ("join_verified", C.c_uint64), ("hot_buckets", C.c_uint64),
+                ("max_depth", C.c_int32), ("reserved", C.c_int32), ("threshold", C.c_double),
+                ("ms_total", C.c_double), ("ms_onepass", C.c_double), ("ms_certify", C.c_double),
+                ("ms_sketch", C.c_double), ("ms_sort", C.c_double), ("ms_probe", C.c_double),
+                ("ms_join", C.c_double), ("ms_rows", C.c_double),
+                ("workspace_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("size", "reserved")}
+
+
+class Debug(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("K", C.c_int32),
+                ("lengths", C.c_void_p), ("depth", C.c_void_p), ("indexed", C.c_void_p),
+                ("mu", C.c_void_p), ("sigma", C.c_void_p), ("profile_pass", C.c_void_p),
+                ("profile_final", C.c_void_p), ("features", C.c_void_p), ("keys", C.c_void_p),
+                ("perm", C.c_void_p), ("bucket_start", C.c_void_p)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("submit_s", C.c_double), ("start_s", C.c_double), ("end_s", C.c_double),
+                ("cells", C.c_uint64), ("workspace_bytes", C.c_uint64)]
+
+
+@dataclass(frozen=True)
+class Motif:
+    i: int
+    j: int
+    m: int
+    dist: float
+
+
+class PMPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libpmp error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpmp.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2607_17481_amd.build` "
+                "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, u64, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64, C.c_size_t
+        L.pmp_default_options.argtypes = [vp]
+        L.pmp_default_options.restype = None
+        L.pmp_last_error.restype = C.c_char_p
+        L.pmp_workspace_bytes.argtypes = [i64, i32, i32, vp]
+        L.pmp_workspace_bytes.restype = sz
+        L.pmp_open.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp]
+        L.pmp_open_ex.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, vp, vp]
+        L.pmp_run_device.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, sz, vp, vp, vp, vp]
+        L.pmp_run_device_debug.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, sz, vp, vp,
+                                           vp, vp, vp]
+        L.pmp_projection.argtypes = [u64, i32, i32, i32]
+        L.pmp_projection.restype = C.c_double
+        L.pmp_calibrate_width.argtypes = [vp, i64, i32, i32, i32, i32, i32, i32, vp]
+        if hasattr(L, "pmp_server_create"):
+            L.pmp_server_create.argtypes = [C.c_int, sz, i32]
+            L.pmp_server_create.restype = vp
+            L.pmp_submit.argtypes = [vp, vp, i64, i32, i32, i32, i32, i32, vp, vp]
+            L.pmp_poll.argtypes = [vp, u64, vp, vp, vp]
+            L.pmp_wait.argtypes = [vp, u64, vp, vp, vp]
+            L.pmp_server_destroy.argtypes = [vp]
+            L.pmp_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != PMP_OK:
+        raise PMPError(rc, lib().pmp_last_error().decode(errors="replace"))
+
+
+def options(**kw) -> Options:
+    o = Options()
+    lib().pmp_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _motifs(buf, n):
+    return [Motif(int(buf[x].i), int(buf[x].j), int(buf[x].m), float(buf[x].dist))
+            for x in range(n)]
+
+
+def open_host(series, m_min: int, m_max: int, k: int, exclusion: int, budget: int = 16,
+              opts: Options | None = None, stats: bool = False):
+    """pmp_open_ex on a host float64 series."""
+    t = np.ascontiguousarray(series, dtype=np.float64)
+    out = (MotifC * max(k, 1))()
+    n_out = C.c_int32(0)
+    st = Stats()
+    st.size = C.sizeof(Stats)
+    rc = lib().pmp_open_ex(t.ctypes.data_as(C.c_void_p), len(t), m_min, m_max, k, exclusion,
+                           budget, C.byref(opts) if opts is not None else None, out,
+                           C.byref(n_out), C.byref(st))
+    _check(rc)
+    res = _motifs(out, n_out.value)
+    return (res, st.as_dict()) if stats else res
+
+
+def workspace_bytes(n: int, m_min: int, m_max: int, opts: Options | None = None) -> int:
+    return int(lib().pmp_workspace_bytes(n, m_min, m_max,
+                                         C.byref(opts) if opts is not None else None))
+
+
+class Workspace:
+    """A torch-owned device workspace for pmp_run_device (grows on demand)."""
+
+    def __init__(self, device="cuda:0"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            torch.cuda.empty_cache()
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self.buf.data_ptr()
+        off = (-ptr) % 256
+        return ptr + off, self.buf.numel() - off
+
+
+def run_device(t_dev, m_min: int, m_max: int, k: int, exclusion: int, budget: int = 16,
+               opts: Options | None = None, workspace: Workspace | None = None, stream=None,
+               debug: Debug | None = None):
+    """pmp_run_device on a torch float64 CUDA tensor; returns (motifs, stats dict)."""
+    import torch
+    assert t_dev.dtype == torch.float64 and t_dev.is_cuda and t_dev.is_contiguous()
+    n = t_dev.numel()
+    ws = workspace or Workspace(t_dev.device)
+    need = workspace_bytes(n, m_min, m_max, opts)
+    if need == 0:
+        raise PMPError(PMP_EINVAL, "invalid arguments for the workspace query")
+    wptr, wbytes = ws.get(need)
+    s = stream if stream is not None else torch.cuda.current_stream(t_dev.device)
+    out = (MotifC * max(k, 1))()
+    n_out = C.c_int32(0)
+    st = Stats()
+    st.size = C.sizeof(Stats)
+    args = [C.c_void_p(t_dev.data_ptr()), n, m_min, m_max, k, exclusion, budget,
+            C.byref(opts) if opts is not None else None, C.c_void_p(wptr), wbytes,
+            C.c_void_p(s.cuda_stream), out, C.byref(n_out), C.byref(st)]
+    if debug is not None:
+        rc = lib().pmp_run_device_debug(*args, C.byref(debug))
+    else:
+        rc = lib().pmp_run_device(*args)
+    _check(rc)
+    return _motifs(out, n_out.value), st.as_dict()
+
+
+def projection(seed: int, m: int, l: int, c: int) -> float:
+    return float(lib().pmp_projection(seed, m, l, c))
+
+
+def calibrate_width(series, m_min, m_max, m_step=1, budget=16, gamma=8, bits=24) -> int:
+    t = np.ascontiguousarray(series, dtype=np.float64)
+    K = C.c_int32(0)
+    _check(lib().pmp_calibrate_width(t.ctypes.data_as(C.c_void_p), len(t), m_min, m_max, m_step,
+                                     budget, gamma, bits, C.byref(K)))
+    return K.value
