@@ -211,3 +211,52 @@ def calibrate_width(series, m_min, m_max, m_step=1, budget=16, gamma=8, bits=24)
     _check(lib().pmp_calibrate_width(t.ctypes.data_as(C.c_void_p), len(t), m_min, m_max, m_step,
                                      budget, gamma, bits, C.byref(K)))
     return K.value
+
+
+class Server:
+    """pmp_server_*: continuous-batching request server (see include/pmp.h)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30, slots: int = 4):
+        self.h = lib().pmp_server_create(device, hbm_budget_bytes, slots)
+        if not self.h:
+            raise PMPError(PMP_EINVAL, "pmp_server_create failed")
+        self._k = {}
+
+    def submit(self, series, m_min, m_max, k, exclusion, budget=16, opts=None) -> int:
+        t = np.ascontiguousarray(series, dtype=np.float64)
+        rid = C.c_uint64(0)
+        _check(lib().pmp_submit(self.h, t.ctypes.data_as(C.c_void_p), len(t), m_min, m_max, k,
+                                exclusion, budget, C.byref(opts) if opts is not None else None,
+                                C.byref(rid)))
+        self._k[rid.value] = k
+        return rid.value
+
+    def _result(self, fn, rid):
+        k = self._k[rid]
+        out = (MotifC * k)()
+        n_out = C.c_int32(0)
+        tm = Timing()
+        rc = fn(self.h, rid, out, C.byref(n_out), C.byref(tm))
+        if rc == PMP_EBUSY:
+            return None
+        self._k.pop(rid, None)
+        _check(rc)
+        timing = {f: getattr(tm, f) for f, _ in Timing._fields_}
+        return _motifs(out, n_out.value), timing
+
+    def poll(self, rid):
+        return self._result(lib().pmp_poll, rid)
+
+    def wait(self, rid):
+        return self._result(lib().pmp_wait, rid)
+
+    def close(self):
+        if self.h:
+            lib().pmp_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

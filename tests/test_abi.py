@@ -1,0 +1,69 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+its headers declare, and its host-only functions behave."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in ("pmp.h", "pmp_stages.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(pmp_[a-z_]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2607_17481_amd import pmp
+    lib = pmp.lib()
+    names = declared_symbols()
+    assert {"pmp_open", "pmp_run_device", "pmp_server_create", "pmp_submit"} <= names
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_options_are_the_paper_constants():
+    from paper_2607_17481_amd import pmp
+    o = pmp.options()
+    assert o.size == C.sizeof(pmp.Options)
+    assert (o.m_step, o.signature_bits, o.gamma, o.probe_ref_depth, o.certify) == (1, 24, 8, 12, 1)
+    assert o.spectral_width == 0 and o.precision == 0
+
+
+def test_workspace_query_and_argument_checks():
+    from paper_2607_17481_amd import pmp
+    assert pmp.workspace_bytes(100_000, 50, 100) > 0
+    assert pmp.workspace_bytes(100_000, 50, 100, pmp.options(precision=1)) < \
+        pmp.workspace_bytes(100_000, 50, 100, pmp.options(precision=0))
+    assert pmp.workspace_bytes(100, 2, 10) == 0          # m_min < 3
+    assert pmp.workspace_bytes(100, 10, 101) == 0        # m_max > n
+    assert pmp.workspace_bytes(100, 20, 10) == 0
+    with pytest.raises(pmp.PMPError) as e:
+        pmp.open_host(np.zeros(10), 2, 5, 3, 1)
+    assert e.value.code == pmp.PMP_EINVAL
+
+
+def test_projection_generator_matches_oracle(oracle):
+    from paper_2607_17481_amd import pmp
+    for seed in (0, 7, 0x5eed2607):
+        for m, l, c in [(3, 0, 0), (50, 23, 29), (4096, 11, 5), (0, 32, 3)]:
+            assert pmp.projection(seed, m, l, c) == oracle.projection(seed, m, l, c)
+
+
+def test_width_calibration_rules():
+    """Sec. 3.2 calibration: smooth windows need few bins, white noise many."""
+    from paper_2607_17481_amd import pmp, synth
+    rng = np.random.default_rng(0)
+    smooth = np.sin(np.arange(20000) * 2 * np.pi / 97.0) + 0.001 * rng.standard_normal(20000)
+    noise = rng.standard_normal(20000)
+    k_smooth = pmp.calibrate_width(smooth, 50, 100)
+    k_noise = pmp.calibrate_width(noise, 50, 100)
+    assert 4 <= k_smooth < k_noise <= 16
+    assert k_noise == 16

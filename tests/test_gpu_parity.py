@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every test here runs libpmp on an MI355X (gfx950) and compares its output
+with the oracle on the same seeded inputs.  Bars: top-k cells and neighbours
+bit-exact (ties within 1e-9 relative allowed), distances within 1e-6
+relative; integer outputs (flags, keys, buckets) exact.
+"""
+import ctypes as C
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2607_17481_amd import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+PRECS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_2607_17481_amd import pmp
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pmp.lib()                                   # fails loudly if libpmp.so is missing
+    return pmp
+
+
+@pytest.fixture(scope="module")
+def ws(gpu):
+    return gpu.Workspace("cuda:0")
+
+
+def run(gpu, ws, t, m_min, m_max, excl, k=20, budget=16, debug=None, **opt):
+    import torch
+    td = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).cuda()
+    o = gpu.options(**opt)
+    print(f"[run] n={len(t)} m={m_min}..{m_max} excl={excl} k={k} opts={opt}", flush=True)
+    return gpu.run_device(td, m_min, m_max, k, excl, budget, o, ws, debug=debug)
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", name + ".json")) as f:
+        return json.load(f)
+
+
+def golden_series(g):
+    if g["generator"] == "random_walk_planted":
+        return synth.random_walk_planted(g["n"], seed=g["seed"])[0]
+    if g["generator"] == "wafer_like":
+        return synth.wafer_like(g["n"], g["seed"])
+    return synth.ecg_like(g["n"], g["seed"])
+
+
+# --------------------------------------------------------------- top-k (a7, a8)
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("name", ["tiny_top20", "wafer100k_top20", "ecg5k_top20"])
+def test_golden_topk(gpu, ws, name, prec):
+    g = golden(name)
+    t = golden_series(g)
+    res, st = run(gpu, ws, t, g["m_min"], g["m_max"], g["exclusion"], g["k"],
+                  m_step=g["m_step"], precision=PRECS[prec])
+    ok, msg = parity.canonical_equal(res, g["top"])
+    assert ok, msg
+    assert st["certify_rounds"] >= 1
+
+
+def test_wafer5m_full_size(gpu, ws, oracle):
+    """The benchmark workload at full size (5M samples x 51 lengths)."""
+    g = golden("wafer5m_top20")
+    t = golden_series(g)
+    res, st = run(gpu, ws, t, 50, 100, 50, 20)
+    ok, msg = parity.canonical_equal(res, g["top"])
+    assert ok, msg
+    for r in res:   # each reported pair recomputed directly by the oracle
+        assert abs(r.i - r.j) >= 50
+        assert oracle.snap(oracle.distance(t, r.m, r.i, r.j)) == r.dist
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_walk_all_lengths_profile_certified(gpu, ws, oracle, prec):
+    """Full oracle profile on a ragged size: every cell the certificate
+    claims exact (value <= T) equals the oracle; the rest is an upper bound."""
+    t = np.cumsum(np.random.default_rng(31).standard_normal(1337))
+    lengths = list(range(12, 40, 3))
+    rows = oracle.pan_profile(t, lengths, 9)
+    cells = sum(len(t) - m + 1 for m in lengths)
+    import torch
+    pf = torch.empty(cells, dtype=torch.float64, device="cuda")
+    pp = torch.empty(cells, dtype=torch.float64, device="cuda")
+    dbg = gpu.Debug()
+    dbg.size = C.sizeof(gpu.Debug)
+    dbg.profile_final = pf.data_ptr()
+    dbg.profile_pass = pp.data_ptr()
+    res, st = run(gpu, ws, t, 12, 39, 9, 20, debug=dbg, m_step=3, precision=PRECS[prec])
+    ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+    assert ok, msg
+    T = st["threshold"]
+    P_or = np.concatenate([rows[m][0] for m in lengths])
+    P_fin = pf.cpu().numpy()
+    P_pass = pp.cpu().numpy()
+    fin = np.isfinite(P_or)
+    # soundness of the one pass (Prop. 1) and of the final profile
+    assert np.all(P_pass[fin] >= P_or[fin] * (1 - 1e-9))
+    assert np.all(np.isinf(P_pass[~fin])) and np.all(np.isinf(P_fin[~fin]))
+    exact = fin & (P_or <= T)
+    assert exact.sum() > 0
+    np.testing.assert_allclose(P_fin[exact], P_or[exact], rtol=1e-9)
+    assert np.all(P_fin[fin] >= P_or[fin] * (1 - 1e-9))
+
+
+# ------------------------------------------------------- stages a1 .. a6
+
+def _debug_arrays(gpu, cells, L, precision, torch, want_keys=True):
+    dbg = gpu.Debug()
+    dbg.size = C.sizeof(gpu.Debug)
+    bufs = {
+        "mu": torch.empty(cells, dtype=torch.float64, device="cuda"),
+        "sigma": torch.empty(cells, dtype=torch.float64, device="cuda"),
+        "features": torch.empty(cells * 32, dtype=torch.float64 if precision == 0 else torch.float32,
+                                device="cuda"),
+        "keys": torch.empty(cells, dtype=torch.int64, device="cuda"),
+        "profile_pass": torch.empty(cells, dtype=torch.float64, device="cuda"),
+    }
+    for k, v in bufs.items():
+        setattr(dbg, k, v.data_ptr())
+    host = {"lengths": np.zeros(L, np.int32), "depth": np.zeros(L, np.int32),
+            "indexed": np.zeros(L, np.int64)}
+    for k, v in host.items():
+        setattr(dbg, k, v.ctypes.data)
+    return dbg, bufs, host
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_moments_features_keys(gpu, ws, oracle, prec):
+    import torch
+    t, _ = synth.random_walk_planted()
+    t = t.copy()
+    t[1000:1100] = t[1000]            # a flat run: constant windows
+    lengths = [32, 57, 82]
+    cells = sum(len(t) - m + 1 for m in lengths)
+    dbg, bufs, host = _debug_arrays(gpu, cells, 51, PRECS[prec], torch)
+    seed = 12345
+    res, st = run(gpu, ws, t, 32, 82, 64, debug=dbg, precision=PRECS[prec], seed=seed,
+                  m_step=25, spectral_width=16)
+    mu = bufs["mu"].cpu().numpy()
+    sig = bufs["sigma"].cpu().numpy()
+    F = bufs["features"].cpu().numpy().astype(np.float64).reshape(cells, 32)
+    keys = bufs["keys"].cpu().numpy().view(np.uint64)
+    base = 0
+    rng = np.random.default_rng(0)
+    for li, m in enumerate(lengths):
+        W = len(t) - m + 1
+        omu, osig, ocst = oracle.window_stats(t, m)
+        # a1: moments (two-pass, same formula) and constant flags
+        np.testing.assert_array_equal(mu[base:base + W][~ocst], omu[~ocst])
+        np.testing.assert_allclose(sig[base:base + W][~ocst], osig[~ocst], rtol=2e-16 * 4)
+        assert np.array_equal(sig[base:base + W] == 0.0, ocst)
+        assert host["indexed"][li] == int((~ocst).sum())
+        # a2: features within the bound the library derives for them
+        for i in rng.choice(np.nonzero(~ocst)[0], size=300, replace=False):
+            fo = oracle.features(t, m, int(i), 16)
+            fg = F[base + i, :30]
+            err = float(np.linalg.norm(fg - fo))
+            e_i = F[base + i, 30]
+            assert err <= e_i, (m, i, err, e_i)
+            assert F[base + i, 31] >= np.linalg.norm(fo) * (1 - 1e-5)
+            if prec == "fp64":
+                assert err <= 1e-9 * m
+            # a3: signature bits where the margin clears the FP32 key error
+            sig_o, marg = oracle.signature(fo, 16, m, 24, seed)
+            kw = int(keys[base + i])
+            tol = 1e-5 * np.linalg.norm(fo) * 6.0 + 2 * e_i * 6.0
+            for b in range(24):
+                if abs(marg[b]) > tol:
+                    assert ((kw >> (23 - b)) & 1) == ((sig_o >> (23 - b)) & 1), (m, i, b)
+        assert np.all(keys[base:base + W][ocst] == np.uint64(0xFFFFFFFFFFFFFFFF))
+        base += W
+
+
+def test_projections_match_oracle_generator(gpu, oracle):
+    for seed in (0, 1, 0x5eed2607):
+        for m in (3, 50, 400):
+            for l in (0, 7, 23):
+                for c in (0, 13, 29):
+                    assert gpu.projection(seed, m, l, c) == oracle.projection(seed, m, l, c)
+
+
+def test_buckets_occupancy_and_order(gpu, ws, oracle):
+    """a4: depth is the final state of global-depth doubling (Prop. 4), each
+    bucket holds the windows whose key prefix is its index, by start."""
+    import torch
+    t = synth.wafer_like(30000, seed=5, copies=4)
+    lengths = list(range(50, 60))
+    cells = sum(len(t) - m + 1 for m in lengths)
+    dbg, bufs, host = _debug_arrays(gpu, cells, len(lengths), 0, torch)
+    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg)       # sizes from the first call
+    N = int(host["indexed"].sum())
+    nb = int(sum(1 << int(d) for d in host["depth"])) + 1
+    perm = torch.empty(N, dtype=torch.int32, device="cuda")
+    bst = torch.empty(nb, dtype=torch.int32, device="cuda")
+    dbg.perm = perm.data_ptr()
+    dbg.bucket_start = bst.data_ptr()
+    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg)
+    perm = perm.cpu().numpy().view(np.uint32).astype(np.int64)
+    bst = bst.cpu().numpy().view(np.uint32).astype(np.int64)
+    keys = bufs["keys"].cpu().numpy().view(np.uint64)
+    alpha = 16
+    cb = 0
+    bb = 0
+    slot = 0
+    for li, m in enumerate(lengths):
+        W = len(t) - m + 1
+        Nm = int(host["indexed"][li])
+        d = int(host["depth"][li])
+        # Prop. 4: smallest d with N <= alpha 2^d; mean occupancy in (alpha/2, alpha]
+        assert Nm <= alpha << d and (d == 0 or Nm > alpha << (d - 1))
+        if d > 0:
+            assert alpha / 2 < Nm / (1 << d) <= alpha
+        _, _, ocst = oracle.window_stats(t, m)
+        assert Nm == int((~ocst).sum())
+        for b in range(1 << d):
+            s0, s1 = bst[bb + b], bst[bb + b + 1]
+            members = perm[s0:s1] - cb
+            assert np.all(np.diff(members) > 0)
+            for i in members[:8]:
+                pre = (int(keys[cb + i]) & 0xFFFFFF) >> (24 - d) if d else 0
+                assert pre == b
+        assert bst[bb] == slot
+        slot += Nm
+        bb += 1 << d
+        cb += W
+    assert bst[bb] == slot == N
+
+
+# ------------------------------------------------ invariances, determinism
+
+def test_result_independent_of_width_budget_seed_precision(gpu, ws, oracle):
+    """Prop. 2 (any width is sound) and the certificate: the exact top-k does
+    not depend on K, alpha, the seed or the feature precision."""
+    t, _ = synth.random_walk_planted(2500, seed=77)
+    rows = oracle.pan_profile(t, range(40, 71, 5), 40)
+    ref = oracle.topk(rows, 20)
+    for kw in [dict(spectral_width=4), dict(spectral_width=8), dict(spectral_width=16),
+               dict(seed=1), dict(seed=99), dict(precision=1), dict(precision=2),
+               dict(signature_bits=8), dict(gamma=1), dict(probe_cap=0)]:
+        for budget in (4, 16, 64):
+            res, _ = run(gpu, ws, t, 40, 70, 40, budget=budget, m_step=5, **kw)
+            ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+            assert ok, (kw, budget, msg)
+            assert [(r.i, r.m) for r in res] == [(x.i, x.m) for x in ref]
+
+
+def test_bitwise_repeatable(gpu, ws):
+    t = synth.wafer_like(50000, seed=8, copies=5)
+    a, _ = run(gpu, ws, t, 50, 70, 50)
+    b, _ = run(gpu, ws, t, 50, 70, 50)
+    assert a == b
+
+
+def test_affine_invariance_and_reversal(gpu, ws, oracle):
+    t = np.cumsum(np.random.default_rng(5).standard_normal(1500))
+    a, _ = run(gpu, ws, t, 20, 30, 15)
+    b, _ = run(gpu, ws, 3.5 * t - 11.0, 20, 30, 15)
+    assert [(x.i, x.j, x.m) for x in a] == [(x.i, x.j, x.m) for x in b]
+    for x, y in zip(a, b):
+        assert parity.dist_close(x.dist, y.dist, 1e-9)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_no_valid_pairs(gpu, ws):
+    t = np.random.default_rng(1).standard_normal(120)
+    res, _ = run(gpu, ws, t, 50, 60, 80)         # W <= excl at every length
+    assert res == []
+
+
+def test_constant_series_has_no_motif(gpu, ws):
+    res, _ = run(gpu, ws, np.full(3000, 2.5), 10, 20, 10)
+    assert res == []
+
+
+def test_fewer_cells_than_k(gpu, ws, oracle):
+    t = np.random.default_rng(2).standard_normal(140)
+    rows = oracle.pan_profile(t, [30], 90)
+    res, _ = run(gpu, ws, t, 30, 30, 90, k=50)
+    ok, msg = parity.check_topk(res, rows, 50, oracle, t)
+    assert ok, msg
+    assert 0 < len(res) < 50
+
+
+def test_duplicates_and_flat_runs(gpu, ws, oracle):
+    rng = np.random.default_rng(4)
+    base = rng.standard_normal(60)
+    t = np.concatenate([rng.standard_normal(300), base, np.zeros(90), 2 * base + 1,
+                        rng.standard_normal(211), base, np.full(40, 3.0)])
+    lengths = range(16, 31, 2)
+    rows = oracle.pan_profile(t, lengths, 20)
+    res, _ = run(gpu, ws, t, 16, 30, 20, m_step=2)
+    ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+    assert ok, msg
+    assert res[0].dist == 0.0
+
+
+@pytest.mark.parametrize("n,lo,hi,excl", [(257, 3, 3, 1), (1001, 3, 9, 2), (777, 64, 64, 64),
+                                          (2049, 100, 130, 33)])
+def test_ragged_and_extreme_lengths(gpu, ws, oracle, n, lo, hi, excl):
+    t = np.cumsum(np.random.default_rng(n).standard_normal(n))
+    rows = oracle.pan_profile(t, range(lo, hi + 1), excl)
+    res, _ = run(gpu, ws, t, lo, hi, excl)
+    ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+    assert ok, msg
+
+
+def test_invalid_arguments(gpu):
+    t = np.random.default_rng(0).standard_normal(100)
+    with pytest.raises(gpu.PMPError) as e:
+        gpu.open_host(t, 2, 10, 5, 5)
+    assert e.value.code == gpu.PMP_EINVAL
+    with pytest.raises(gpu.PMPError):
+        gpu.open_host(t, 10, 101, 5, 5)
+    bad = t.copy()
+    bad[17] = np.nan
+    with pytest.raises(gpu.PMPError) as e:
+        gpu.open_host(bad, 10, 20, 5, 5)
+    assert e.value.code == gpu.PMP_EINVAL
+
+
+def test_open_host_matches_device_path(gpu, ws):
+    t, _ = synth.random_walk_planted()
+    g = golden("tiny_top20")
+    res = gpu.open_host(t, 32, 82, 20, 64)
+    ok, msg = parity.canonical_equal(res, g["top"])
+    assert ok, msg
