@@ -143,12 +143,12 @@ __device__ __forceinline__ uint32_t jquant(float p, float R, int jshift) {
 __global__ __launch_bounds__(kBlock) void k_join_keys(Req q, const float *__restrict__ prange,
                                                       int64_t N, uint32_t *__restrict__ jk,
                                                       uint32_t *__restrict__ jv) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= N) return;
-    const int l = find_len_slot(q.len, q.L, s);
-    const float p = q.jrec[s * 8];
-    jk[s] = ((uint32_t)l << q.jkey_shift) | jquant(p, prange[l], q.jkey_shift);
-    jv[s] = (uint32_t)s;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= N) return;
+    const int l = find_len_k(q.len, q.L, k);
+    const float p = q.jrec[k * 8];
+    jk[k] = ((uint32_t)l << q.jkey_shift) | jquant(p, prange[l], q.jkey_shift);
+    jv[k] = (uint32_t)k;
 }
 
 __global__ __launch_bounds__(kBlock) void k_join_gather(const float *__restrict__ jrec,
@@ -162,71 +162,120 @@ __global__ __launch_bounds__(kBlock) void k_join_gather(const float *__restrict_
     dst[1] = src[1];
 }
 
-// One lane per sorted position.  The query's own cell is lowered through an
-// atomic min (each pair is reached from both of its cells).
+// One lane per sorted position searches its band (lane-parallel filters and
+// bounds); the wavefront verifies the proposals one per lane per round with
+// the canonical distance.  The exact distance lowers both cells.
+// Join queries: the indexed windows not yet at 0, in (length, start) order,
+// as positions of the join order (wave-aggregated append).
+__global__ __launch_bounds__(kBlock) void k_join_queries(Req q, const uint32_t *__restrict__ jinv,
+                                                         int64_t N, uint32_t *__restrict__ jq,
+                                                         uint32_t *__restrict__ count) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool want = k < N && q.P[k] != 0ull;
+    const uint64_t bal = __ballot(want);
+    uint32_t base = 0;
+    if (lane_id() == 0 && bal) base = atomicAdd(count, (uint32_t)__popcll(bal));
+    base = __shfl(base, 0, kWave);
+    if (want) jq[base + __popcll(bal & lanemask_lt())] = jinv[k];
+}
+
 template <typename FT>
 __global__ __launch_bounds__(kBlock) void k_join(Req q, const float *__restrict__ js,
                                                  const uint32_t *__restrict__ jkey,
-                                                 const JoinLen *__restrict__ jl, int64_t N,
-                                                 double T) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                 const JoinLen *__restrict__ jl,
+                                                 const uint32_t *__restrict__ jq, int64_t nq,
+                                                 int64_t N, double T) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
-    if (p < N) {
+    bool done = k >= nq;
+    const int64_t p = done ? 0 : (int64_t)jq[k];
+    uint32_t kq = 0, klo = 0, khi = 0;
+    double Pq = 0.0, muq = 0.0, isq = 0.0;
+    int m = 0;
+    int64_t iq = 0, cell_base = 0;
+    float sqrt2m = 0.0f, rf2 = 0.0f;
+    bool inf_r = false;
+    float pq[kJoinDims];
+    const FT *fq = (const FT *)q.F;
+    if (!done) {
         const float *rq = js + p * 8;
-        const uint32_t sq = __float_as_uint(rq[6]);
-        const uint32_t cq = q.perm[sq];
-        double Pq = bitsd(q.P[cq]);
-        if (Pq > 0.0) {
-            const int l = find_len_slot(q.len, q.L, sq);
+        kq = __float_as_uint(rq[6]);
+        Pq = bitsd(q.P[kq]);
+        done = Pq == 0.0;
+        if (!done) {
+            const int l = find_len_k(q.len, q.L, kq);
             const LenInfo L = q.len[l];
             const JoinLen J = jl[l];
-            const int m = L.m;
-            const int kp = L.kprime;
-            const float sqrt2m = (float)sqrt(2.0 / (double)m) * (1.0f + 1e-7f);
-            const int64_t iq = (int64_t)cq - L.cell_base;
-            const double muq = q.mu[cq], isq = q.isig[cq];
-            const FT *fq = (const FT *)q.F + (int64_t)sq * kRec;
-            float pq[kJoinDims];
+            m = L.m;
+            cell_base = L.cell_base;
+            sqrt2m = (float)sqrt(2.0 / (double)m) * (1.0f + 1e-7f);
+            iq = (int64_t)q.cell[kq] - cell_base;
+            muq = q.mu[kq];
+            isq = q.isig[kq];
+            fq += (int64_t)kq * kRec;
 #pragma unroll
-            for (int k = 0; k < kJoinDims; ++k) pq[k] = rq[k];
+            for (int x = 0; x < kJoinDims; ++x) pq[x] = rq[x];
             const uint32_t lbase = (uint32_t)l << q.jkey_shift;
-            const bool inf_r = !isfinite(J.r_key);
-            const uint32_t klo = inf_r ? lbase : lbase | jquant(pq[0] - J.r_key, J.prange, q.jkey_shift);
-            const uint32_t khi = inf_r ? (lbase | ((1u << q.jkey_shift) - 1u))
-                                       : lbase | jquant(pq[0] + J.r_key, J.prange, q.jkey_shift);
-            const float rf2 = J.r_filter * J.r_filter;
-            for (int dir = 0; dir < 2; ++dir) {
-                for (int64_t c = dir == 0 ? p - 1 : p + 1; c >= 0 && c < N; c += dir == 0 ? -1 : 1) {
-                    const uint32_t key = jkey[c];
-                    if (key < klo || key > khi) break;
-                    const float *rc = js + c * 8;
-                    float s2 = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < kJoinDims; ++k) {
-                        float e = rc[k] - pq[k];
-                        s2 = fmaf(e, e, s2);
-                    }
-                    if (!(s2 <= rf2) && !inf_r) continue;
-                    const uint32_t sc = __float_as_uint(rc[6]);
-                    const uint32_t cc = q.perm[sc];
-                    const int64_t ic = (int64_t)cc - L.cell_base;
-                    const int64_t gap = ic > iq ? ic - iq : iq - ic;
-                    if (gap < q.excl) continue;
-                    ++n_cand;
-                    const FT *fc = (const FT *)q.F + (int64_t)sc * kRec;
-                    const float lb = lb_safe<FT>(fq, fc, kp, sqrt2m);
-                    if ((double)lb > T || (double)lb >= Pq) continue;
-                    ++n_ver;
-                    const double dd = snap(zdist(q.t, iq, muq, isq, ic, q.mu[cc], q.isig[cc], m));
-                    if (dd < Pq) {
-                        atomicMin((unsigned long long *)&q.P[cq], (unsigned long long)dbits(dd));
-                        Pq = dd;
-                        if (Pq == 0.0) break;
-                    }
-                }
-                if (Pq == 0.0) break;
-            }
+            inf_r = !isfinite(J.r_key);
+            klo = inf_r ? lbase : lbase | jquant(pq[0] - J.r_key, J.prange, q.jkey_shift);
+            khi = inf_r ? (lbase | ((1u << q.jkey_shift) - 1u))
+                        : lbase | jquant(pq[0] + J.r_key, J.prange, q.jkey_shift);
+            rf2 = J.r_filter * J.r_filter;
         }
+    }
+    int dir = 0;
+    int64_t c = p - 1;
+    bool has = false;
+    uint32_t pc = 0;
+    int64_t pic = 0;
+    double pmu = 0.0, pis = 0.0;
+    for (;;) {
+        while (!done && !has) {
+            if (dir == 0) {
+                if (c < 0 || jkey[c] < klo) { dir = 1; c = p + 1; continue; }
+            } else if (c >= N || jkey[c] > khi) {
+                done = true;
+                break;
+            }
+            const int64_t cur = c;
+            c += dir == 0 ? -1 : 1;
+            const float *rc = js + cur * 8;
+            if (!inf_r) {
+                float s2 = 0.0f;
+#pragma unroll
+                for (int x = 0; x < kJoinDims; ++x) {
+                    const float e = rc[x] - pq[x];
+                    s2 = fmaf(e, e, s2);
+                }
+                if (!(s2 <= rf2)) continue;
+            }
+            const uint32_t kc = __float_as_uint(rc[6]);
+            const int64_t ic = (int64_t)q.cell[kc] - cell_base;
+            const int64_t gap = ic > iq ? ic - iq : iq - ic;
+            if (gap < q.excl) continue;
+            ++n_cand;
+            const float lb = lb_mem<FT>(fq, (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
+            if ((double)lb > T || (double)lb >= Pq) continue;
+            has = true;
+            pc = kc;
+            pic = ic;
+            pmu = q.mu[kc];
+            pis = q.isig[kc];
+        }
+        const uint64_t mask = __ballot(has);
+        if (mask == 0) break;
+        verify_proposals(mask, q.t, iq, muq, isq, pic, pmu, pis, m,
+                         [&](double dd) {
+                             ++n_ver;
+                             const unsigned long long db = (unsigned long long)dbits(dd);
+                             if (dd < Pq) {
+                                 atomicMin((unsigned long long *)&q.P[kq], db);
+                                 Pq = dd;
+                             }
+                             atomicMin((unsigned long long *)&q.P[pc], db);
+                             has = false;
+                             if (Pq == 0.0) done = true;
+                         });
     }
     unsigned long long a = n_cand, v = n_ver;
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -243,44 +292,54 @@ __global__ __launch_bounds__(kBlock) void k_join(Req q, const float *__restrict_
 
 // Pass 1 (find_min = 1): out_min[c] = min over valid j of the snapped
 // distance.  Pass 2: out_arg[c] = smallest valid j whose snapped distance
-// equals req[c].target.
+// equals req[c].target.  Constant windows are not indexed and never scanned.
+// Each 16-lane group takes every (groups)-th window of the length.
 __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict__ rr, int find_min,
                                                  unsigned long long *__restrict__ out_min,
                                                  unsigned long long *__restrict__ out_arg) {
     const RowReq R = rr[blockIdx.y];
     const LenInfo L = q.len[R.l];
     const int m = L.m;
-    const int64_t i = R.i;
-    const int64_t ci = L.cell_base + i;
-    const double mui = q.mu[ci], isi = q.isig[ci];
-    __shared__ unsigned long long red[kBlock / kWave];
+    const int64_t i = (int64_t)q.cell[R.k] - L.cell_base;
+    const double mui = q.mu[R.k], isi = q.isig[R.k];
+    constexpr int kGroupsPerBlock = kBlock / kGroup;
+    const int64_t g0 = (int64_t)blockIdx.x * kGroupsPerBlock + threadIdx.x / kGroup;
+    const int64_t ng = (int64_t)gridDim.x * kGroupsPerBlock;
+    // every group runs the same number of iterations (uniform control flow)
+    const int64_t iters = (L.n_index + ng - 1) / ng;
     unsigned long long best = find_min ? (unsigned long long)kInfBits : ~0ull;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < L.W;
-         j += (int64_t)gridDim.x * kBlock) {
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t x = g0 + it * ng;
+        bool ok = x < L.n_index;
+        const int64_t kc = L.kbase + (ok ? x : 0);
+        const int64_t j = (int64_t)q.cell[kc] - L.cell_base;
         const int64_t gap = j > i ? j - i : i - j;
-        if (gap < q.excl) continue;
-        const int64_t cj = L.cell_base + j;
-        const double isj = q.isig[cj];
-        if (isj == 0.0) continue;
-        const double dd = snap(zdist(q.t, i, mui, isi, j, q.mu[cj], isj, m));
-        if (find_min) {
-            unsigned long long b = (unsigned long long)dbits(dd);
-            best = b < best ? b : best;
-        } else if (dbits(dd) == R.target) {
-            best = (unsigned long long)j < best ? (unsigned long long)j : best;
+        ok = ok && gap >= q.excl;
+        const double dd = snap(group_zdist(q.t, i, mui, isi, ok ? j : i, ok ? q.mu[kc] : 0.0,
+                                           ok ? q.isig[kc] : 0.0, ok ? m : 0));
+        if (ok) {
+            const unsigned long long b = (unsigned long long)dbits(dd);
+            if (find_min) best = b < best ? b : best;
+            else if (b == R.target && (unsigned long long)j < best) best = (unsigned long long)j;
         }
     }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        unsigned long long o = __shfl_xor(best, off, kWave);
+    // all lanes of a group hold the same value; reduce across the wave
+    for (int off = kGroup; off < kWave; off <<= 1) {
+        const unsigned long long o = __shfl_xor(best, off, kWave);
         best = o < best ? o : best;
     }
-    if (lane_id() == 0) red[threadIdx.x / kWave] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < kBlock / kWave; ++k) best = red[k] < best ? red[k] : best;
+    if (lane_id() == 0) {
         if (find_min) atomicMin(&out_min[blockIdx.y], best);
-        else atomicMin(&out_arg[blockIdx.y], best);
+        else if (best != ~0ull) atomicMin(&out_arg[blockIdx.y], best);
     }
+}
+
+// out[x] = src[idx[x]]
+__global__ __launch_bounds__(kBlock) void k_gather_u32(const uint32_t *__restrict__ src,
+                                                       const uint32_t *__restrict__ idx, int64_t n,
+                                                       uint32_t *__restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (x < n) out[x] = src[idx[x]];
 }
 
 // ------------------------------------------------------------ utilities
@@ -335,20 +394,34 @@ void launch_join_gather(const float *jrec, const uint32_t *jperm, int64_t N, flo
                            jsorted);
 }
 
-void launch_join(int precision, const Req &q, const float *js, const uint32_t *jkey,
-                 const JoinLen *jl, int64_t N, double T, hipStream_t s) {
-    if (N <= 0) return;
-    if (precision == 0)
-        hipLaunchKernelGGL(k_join<double>, dim3(nblk(N)), dim3(kBlock), 0, s, q, js, jkey, jl, N, T);
-    else
-        hipLaunchKernelGGL(k_join<float>, dim3(nblk(N)), dim3(kBlock), 0, s, q, js, jkey, jl, N, T);
+void launch_join_queries(const Req &q, const uint32_t *jinv, int64_t N, uint32_t *jq,
+                         uint32_t *count, hipStream_t s) {
+    if (N > 0)
+        hipLaunchKernelGGL(k_join_queries, dim3(nblk(N)), dim3(kBlock), 0, s, q, jinv, N, jq, count);
 }
 
-void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxW, int find_min,
+void launch_join(int precision, const Req &q, const float *js, const uint32_t *jkey,
+                 const JoinLen *jl, const uint32_t *jq, int64_t nq, int64_t N, double T,
+                 hipStream_t s) {
+    if (nq <= 0) return;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_join<double>, dim3(nblk(nq)), dim3(kBlock), 0, s, q, js, jkey, jl, jq,
+                           nq, N, T);
+    else
+        hipLaunchKernelGGL(k_join<float>, dim3(nblk(nq)), dim3(kBlock), 0, s, q, js, jkey, jl, jq,
+                           nq, N, T);
+}
+
+void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s) {
     if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_rows, dim3(gridcap(maxW, 1024), (unsigned)nrows), dim3(kBlock), 0, s, q,
-                       rr, find_min, out_min, out_arg);
+    hipLaunchKernelGGL(k_rows, dim3(gridcap(maxN / 4, 1024), (unsigned)nrows), dim3(kBlock), 0, s,
+                       q, rr, find_min, out_min, out_arg);
+}
+
+void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,
+                       hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gather_u32, dim3(nblk(n)), dim3(kBlock), 0, s, src, idx, n, out);
 }
 
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {

@@ -18,6 +18,11 @@
 // their bit patterns), which is order independent, so the profile does not
 // depend on the schedule (the role of the fixed merge order of Prop. 5).
 //
+// GPU mapping: one lane per query searches its candidates (lane-parallel
+// bound tests); the exact distances of the proposals (one per lane per round)
+// are computed four at a time by the 16-lane groups of the wavefront, with
+// contiguous loads (group_zdist).
+//
 // One departure from the paper: a query stops once its own cell reaches 0
 // (the smallest possible value); the remaining candidates could only lower
 // their own cells, which their own queries, or the certificate, cover.
@@ -25,79 +30,126 @@
 
 namespace pmp {
 
+// Queries are taken in (length, start) order (indexed position k), so that
+// neighbouring windows, which tend to cost alike, share a wavefront.
 template <typename FT>
 __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restrict__ bstart,
                                                   int64_t N) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
-    if (s < N) {
-        const int l = find_len_slot(q.len, q.L, s);
+    int64_t s = 0;
+
+    // ---- per-lane query state
+    bool done = k >= N;
+    int m = 0, d = 0, probes = 0;
+    int64_t cell_base = 0;
+    uint32_t cq = 0, prefix = 0, lim = 0;
+    int64_t iq = 0;
+    uint64_t kw = 0;
+    double Pq = 0.0, muq = 0.0, isq = 0.0;
+    float sqrt2m = 0.0f;
+    const uint32_t *bb = bstart;
+    const FT *fq = (const FT *)q.F;
+    if (!done) {
+        const int l = find_len_k(q.len, q.L, k);
         const LenInfo L = q.len[l];
-        const int m = L.m;
-        const int d = L.depth;
-        const int kp = L.kprime;
-        const float sqrt2m = (float)sqrt(2.0 / (double)m) * (1.0f + 1e-7f);
-        const uint32_t cq = q.perm[s];
-        const int64_t iq = (int64_t)cq - L.cell_base;
-        const uint64_t kw = q.keyw[s];
-        const uint32_t sig = (uint32_t)(kw & 0xFFFFFFu);
-        const uint32_t prefix = d ? sig >> (q.B - d) : 0u;
-        const FT *fq = (const FT *)q.F + s * kRec;
-        double Pq = bitsd(q.P[cq]);
-        const double muq = q.mu[cq], isq = q.isig[cq];
-        const int64_t last_valid = iq - q.excl;          // candidates i <= iq - excl
-        int budget = q.budget_R;
-        const uint32_t *bb = bstart + L.bucket_base;
-        for (int pr = 0; pr <= L.probes && budget > 0 && Pq > 0.0; ++pr) {
-            uint32_t b = prefix;
-            if (pr > 0) {
-                const int bit = (int)((kw >> (24 + 5 * (pr - 1))) & 31u);
-                b = prefix ^ (1u << (d - 1 - bit));
-            }
-            const int64_t bs = bb[b], be = bb[b + 1];
-            if (be <= bs || last_valid < 0) continue;
-            // first entry with start > last_valid
-            int64_t lo = bs, hi = be;
-            const uint32_t lim = (uint32_t)(L.cell_base + last_valid);
-            while (lo < hi) {
-                int64_t mid = (lo + hi) >> 1;
-                if (q.perm[mid] <= lim) lo = mid + 1; else hi = mid;
-            }
-            const int64_t cut = lo;
-            const int64_t cnt = cut - bs;
-            if (cnt <= 0) continue;
-            int take, rec;
-            int64_t strided_span;
-            if (cnt <= budget) {
-                take = (int)cnt; rec = take; strided_span = 0;
-            } else {
-                take = budget; rec = budget - budget / 2; strided_span = cnt - rec;
-            }
-            const int str = take - rec;
-            budget -= take;
-            for (int j = 0; j < take && Pq > 0.0; ++j) {
-                int64_t cs;
-                if (j < rec) cs = cut - 1 - j;                         // most recent first
-                else cs = bs + ((int64_t)(j - rec) * strided_span) / str;   // even intervals
-                ++n_cand;
-                const uint32_t cc = q.perm[cs];
-                const double Pc = bitsd(q.P[cc]);
-                const double thr = fmax(Pq, Pc);
-                if (thr == 0.0) continue;
-                const FT *fc = (const FT *)q.F + cs * kRec;
-                const float lb = lb_safe<FT>(fq, fc, kp, sqrt2m);
-                if ((double)lb >= thr) continue;
-                ++n_ver;
-                const double dd = snap(zdist(q.t, iq, muq, isq, (int64_t)cc - L.cell_base,
-                                             q.mu[cc], q.isig[cc], m));
-                const uint64_t db = dbits(dd);
-                if (dd < Pq) {
-                    atomicMin((unsigned long long *)&q.P[cq], (unsigned long long)db);
-                    Pq = dd;
+        m = L.m;
+        d = L.depth;
+        probes = L.probes;
+        cell_base = L.cell_base;
+        bb = bstart + L.bucket_base;
+        sqrt2m = (float)sqrt(2.0 / (double)m) * (1.0f + 1e-7f);
+        cq = q.cell[k];
+        s = q.inv[k];
+        iq = (int64_t)cq - cell_base;
+        kw = q.keyw[k];
+        prefix = d ? (uint32_t)(kw & 0xFFFFFFu) >> (q.B - d) : 0u;
+        Pq = bitsd(q.P[k]);
+        muq = q.mu[k];
+        isq = q.isig[k];
+        fq += k * kRec;
+        done = Pq == 0.0 || iq - q.excl < 0;
+        lim = (uint32_t)(cell_base + iq - q.excl);
+    }
+    // candidate iterator
+    int pr = -1, budget = q.budget_R;
+    int64_t bs = 0, cut = 0, span = 0;
+    int take = 0, rec = 0, str = 1, j = 0;
+    // current proposal
+    bool has = false;
+    uint32_t pc = 0;
+    int64_t pic = 0;
+    double pPc = 0.0, pmu = 0.0, pis = 0.0;
+
+    for (;;) {
+        // ---- each lane advances to its next candidate that survives the prune
+        while (!done && !has) {
+            if (j >= take) {
+                // open the next bucket
+                ++pr;
+                if (pr > probes || budget <= 0) { done = true; break; }
+                uint32_t b = prefix;
+                if (pr > 0) {
+                    const int bit = (int)((kw >> (24 + 5 * (pr - 1))) & 31u);
+                    b = prefix ^ (1u << (d - 1 - bit));
                 }
-                if (dd < Pc) atomicMin((unsigned long long *)&q.P[cc], (unsigned long long)db);
+                bs = bb[b];
+                if (pr == 0) {
+                    // own bucket: the query sits at slot s; the earlier valid
+                    // entries end just before those within excl of it
+                    cut = s;
+                    while (cut > bs && q.pcell[cut - 1] > lim) --cut;
+                } else {
+                    int64_t lo = bs, hi = bb[b + 1];
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi) >> 1;
+                        if (q.pcell[mid] <= lim) lo = mid + 1; else hi = mid;
+                    }
+                    cut = lo;
+                }
+                const int64_t cnt = cut - bs;
+                j = 0;
+                if (cnt <= 0) { take = 0; continue; }
+                if (cnt <= budget) {
+                    take = (int)cnt; rec = take; span = 0;
+                } else {
+                    take = budget; rec = budget - budget / 2; span = cnt - rec;
+                }
+                str = take - rec > 0 ? take - rec : 1;
+                budget -= take;
+                continue;
             }
+            const int64_t cs = j < rec ? cut - 1 - j : bs + ((int64_t)(j - rec) * span) / str;
+            ++j;
+            ++n_cand;
+            const uint32_t kc = q.perm[cs];
+            const double Pc = bitsd(q.P[kc]);
+            const double thr = fmax(Pq, Pc);
+            if (thr == 0.0) continue;
+            const float lb = lb_mem<FT>(fq, (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
+            if ((double)lb >= thr) continue;
+            has = true;
+            pc = kc;
+            pic = (int64_t)q.pcell[cs] - cell_base;
+            pPc = Pc;
+            pmu = q.mu[kc];
+            pis = q.isig[kc];
         }
+        // ---- the wavefront verifies the proposals, four at a time
+        const uint64_t mask = __ballot(has);
+        if (mask == 0) break;
+        verify_proposals(mask, q.t, iq, muq, isq, pic, pmu, pis, m,
+                         [&](double dd) {
+                             ++n_ver;
+                             const unsigned long long db = (unsigned long long)dbits(dd);
+                             if (dd < Pq) {
+                                 atomicMin((unsigned long long *)&q.P[k], db);
+                                 Pq = dd;
+                             }
+                             if (dd < pPc) atomicMin((unsigned long long *)&q.P[pc], db);
+                             has = false;
+                             if (Pq == 0.0) done = true;
+                         });
     }
     // stats: one atomic per wave
     unsigned long long a = n_cand, v = n_ver;
@@ -110,7 +162,6 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
         if (v) atomicAdd(&q.counters[C_PASS_VER], v);
     }
 }
-
 
 // Buckets holding more than R entries (hot classes, Sec. 3.6) -- statistics.
 __global__ __launch_bounds__(kBlock) void k_hot_buckets(const uint32_t *__restrict__ bstart,

@@ -7,9 +7,9 @@
 // one sliding state per length and updates it in O(K) per slide
 //   X_{i+1,k} = e^{2 pi i k / m} (X_{i,k} - t_i + t_{i+m}),
 // recomputing from the raw samples every 4096 slides.  On the GPU each block
-// takes a tile of 256 consecutive windows of one length, staged in LDS; the
-// tile is split into 16 segments of 16 windows, and thread (segment, bin)
-// computes its bin directly at the segment start and slides it 15 times, in
+// takes a tile of 1024 consecutive windows of one length, staged in LDS; the
+// tile is split into 16 segments of 64 windows, and thread (segment, bin)
+// computes its bin directly at the segment start and slides it 63 times, in
 // FP64.  Samples are shifted by a per-segment constant c first, which leaves
 // every bin k >= 1 unchanged (Lemma 1) and keeps the magnitudes small.
 //
@@ -19,10 +19,10 @@
 // magnitude (replacing the paper's relative (1 - lambda) shrink, Lemma 4,
 // which it proves only above a threshold).
 //
-// Pass A writes the window moments and the key word (signature bits plus the
-// Hamming-1 probe order); pass B, after the bucket sort, recomputes the same
-// features and writes them in bucket (slot) order together with the join
-// record.
+// One pass writes, for every non-constant window k (compacted, in (length,
+// start) order): its cell, moments, feature record, key word (signature +
+// Hamming-1 probe order), join record and bucket sort key.  Records are
+// staged in LDS and leave in whole, coalesced rows.
 #include "pmp_dev.h"
 
 namespace pmp {
@@ -45,25 +45,6 @@ __global__ __launch_bounds__(kBlock) void k_changepoints(const double *__restric
     flag[r] = f;
 }
 
-// Non-constant windows per length: window [i, i+m) is constant iff no change
-// point lies in (i, i+m), i.e. E[i+m] == E[i+1] for the exclusive prefix E.
-__global__ __launch_bounds__(kBlock) void k_count_index(const LenInfo *__restrict__ len,
-                                                        const uint32_t *__restrict__ E,
-                                                        unsigned long long *__restrict__ cnt) {
-    const int l = blockIdx.y;
-    const int m = len[l].m;
-    const int64_t W = len[l].W;
-    unsigned long long c = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < W;
-         i += (int64_t)gridDim.x * kBlock)
-        c += E[i + m] != E[i + 1];
-    // wave reduction then one atomic per wave
-    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-    if (lane_id() == 0 && c) atomicAdd(&cnt[l], c);
-}
-
-// ---------------------------------------------------------------- sketch
-
 namespace {
 
 __device__ __forceinline__ int find_tile_len(const LenInfo *len, int L, int64_t tile) {
@@ -75,21 +56,56 @@ __device__ __forceinline__ int find_tile_len(const LenInfo *len, int L, int64_t 
     return lo;
 }
 
+}  // namespace
+
+// Non-constant windows per tile: window [i, i+m) is constant iff no change
+// point lies in (i, i+m), i.e. E[i+m] == E[i+1] for the exclusive prefix E.
+__global__ __launch_bounds__(kBlock) void k_tile_counts(const LenInfo *__restrict__ len, int L,
+                                                        const uint32_t *__restrict__ E,
+                                                        uint32_t *__restrict__ tile_cnt) {
+    __shared__ uint32_t ws[kBlock / kWave];
+    const int64_t tile = blockIdx.x;
+    const int l = find_tile_len(len, L, tile);
+    const int m = len[l].m;
+    const int64_t i0 = (tile - len[l].tile_base) * kTileW;
+    const int nw = (int)min<int64_t>(kTileW, len[l].W - i0);
+    uint32_t c = 0;
+    for (int w = threadIdx.x; w < nw; w += kBlock) c += E[i0 + w + m] != E[i0 + w + 1];
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if (lane_id() == 0) ws[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_cnt[tile] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// ---------------------------------------------------------------- sketch
+
+namespace {
+
+constexpr int kFD = 2 * (kMaxK - 1);      // 30 feature reals
+constexpr int kRows = kSegs * kChunk;     // windows per post-processing step (64)
+
 struct SketchSmem {
-    double mu[kTileW];
     double isig[kTileW];
-    float ymax[kTileW / kSegW];
-    float f[kTileW][kRec + 1];   // +1 pads the row to avoid bank conflicts
-    float g[kMaxBits][2 * (kMaxK - 1)];
-    uint32_t wcount[kBlock / kWave];
+    int32_t kpos[kTileW];                 // indexed position, -1 for constant windows
+    float ymax[kSegs];
+    float mg[kRows][kMaxBits + 1];        // |<g_l, F>| of each row
+    float g[kMaxBits][kFD];
+    uint32_t wsum[kBlock / kWave];
+    int emax;
 };
 
 }  // namespace
 
-template <int PASS, typename FT>
-__global__ __launch_bounds__(kBlock) void k_sketch(Req q, const uint32_t *__restrict__ E,
-                                                   uint32_t *__restrict__ tile_cnt) {
-    extern __shared__ double st[];                 // tile samples, 256 + m - 1
+// One block per tile of 1024 consecutive windows of one length.  Thread
+// (segment g = tid / 16, bin b = tid % 16) owns bin k = b + 1 of the 64
+// windows of segment g: it computes the bin directly at the segment start
+// (four independent phasor chains, so the sum is not one long dependent
+// chain) and slides it 63 times.  Every 4 slides the 64 new windows are
+// post-processed by four threads each.
+template <typename FT>
+__global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__restrict__ E,
+                                                      const uint32_t *__restrict__ tile_off) {
+    extern __shared__ double dyn[];
     __shared__ SketchSmem sm;
     const int64_t tile = blockIdx.x;
     const int l = find_tile_len(q.len, q.L, tile);
@@ -99,233 +115,307 @@ __global__ __launch_bounds__(kBlock) void k_sketch(Req q, const uint32_t *__rest
     const int64_t i0 = (tile - L.tile_base) * kTileW;
     const int nw = (int)min<int64_t>(kTileW, L.W - i0);
     const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid / kWave;
+    double *st = dyn;                                        // samples, 1024 + m - 1
+    FT(*stage)[kRec + 1] = (FT(*)[kRec + 1])(dyn + kTileW + m);   // then kRows records
 
+    if (tid == 0) sm.emax = 0;
     for (int r = tid; r < nw + m - 1; r += kBlock) st[r] = q.t[i0 + r];
-    if (PASS == 0) {
-        for (int c = tid; c < q.B * 2 * (kMaxK - 1); c += kBlock)
-            sm.g[c / (2 * (kMaxK - 1))][c % (2 * (kMaxK - 1))] =
-                q.gproj[((int64_t)l * q.B) * 2 * (kMaxK - 1) + c];
-    }
+    for (int c = tid; c < q.B * kFD; c += kBlock)
+        sm.g[c / kFD][c % kFD] = q.gproj[(int64_t)l * q.B * kFD + c];
     __syncthreads();
 
-    // ---- moments: two-pass population mean / standard deviation (Sec. 3.2)
-    if (tid < nw) {
-        const int64_t cell = L.cell_base + i0 + tid;
-        double mu = 0.0, is = 0.0;
-        if (PASS == 0) {
-            const bool cst = E[i0 + tid + m] == E[i0 + tid + 1];
-            if (!cst) {
-#pragma clang fp contract(off)
-                double s = 0.0;
-                for (int r = 0; r < m; ++r) s += st[tid + r];
-                mu = s / (double)m;
-                double qq = 0.0;
-                for (int r = 0; r < m; ++r) {
-                    double c = st[tid + r] - mu;
-                    qq += c * c;
+    // ---- moments (two-pass, population; Sec. 3.2) and compacted positions
+    {
+        uint32_t run = tile_off[tile];
+        for (int w0 = 0; w0 < kTileW; w0 += kBlock) {
+            const int w = w0 + tid;
+            const bool in = w < nw;
+            const bool ix = in && E[i0 + w + m] != E[i0 + w + 1];
+            const uint64_t bal = __ballot(ix);
+            if (lane == 0) sm.wsum[wv] = (uint32_t)__popcll(bal);
+            __syncthreads();
+            uint32_t pos = run + (uint32_t)__popcll(bal & lanemask_lt()), tot = 0;
+            for (int x = 0; x < kBlock / kWave; ++x) {
+                if (x < wv) pos += sm.wsum[x];
+                tot += sm.wsum[x];
+            }
+            double is = 0.0;
+            if (ix) {
+                // four partial sums per pass keep the LDS loads independent
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int r = 0;
+                for (; r + 4 <= m; r += 4) {
+                    a0 += st[w + r];
+                    a1 += st[w + r + 1];
+                    a2 += st[w + r + 2];
+                    a3 += st[w + r + 3];
                 }
-                double sg = sqrt(qq / (double)m);
+                for (; r < m; ++r) a0 += st[w + r];
+                const double mu = ((a0 + a1) + (a2 + a3)) / (double)m;
+                a0 = a1 = a2 = a3 = 0.0;
+                for (r = 0; r + 4 <= m; r += 4) {
+                    const double c0 = st[w + r] - mu, c1 = st[w + r + 1] - mu;
+                    const double c2 = st[w + r + 2] - mu, c3 = st[w + r + 3] - mu;
+                    a0 = fma(c0, c0, a0);
+                    a1 = fma(c1, c1, a1);
+                    a2 = fma(c2, c2, a2);
+                    a3 = fma(c3, c3, a3);
+                }
+                for (; r < m; ++r) {
+                    const double c0 = st[w + r] - mu;
+                    a0 = fma(c0, c0, a0);
+                }
+                const double sg = sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
                 is = 1.0 / sg;
                 if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
-                    // samples differ but sigma underflows: outside the range
-                    // the library represents; keep the window indexed so
-                    // every count stays consistent and report the input
+                    // samples differ but sigma underflows or overflows:
+                    // outside the range the library represents; keep the
+                    // window indexed so every count stays consistent
                     atomicOr(q.bad, 2);
                     is = 1.0;
                 }
-            } else {
-                mu = st[tid];
+                q.cell[pos] = (uint32_t)(L.cell_base + i0 + w);
+                q.mu[pos] = mu;
+                q.isig[pos] = is;
+                q.P[pos] = kInfBits;
             }
-            q.mu[cell] = mu;
-            q.isig[cell] = is;
-        } else {
-            mu = q.mu[cell];
-            is = q.isig[cell];
+            if (in) {
+                sm.isig[w] = is;
+                sm.kpos[w] = ix ? (int32_t)pos : -1;
+            }
+            run += tot;
+            __syncthreads();
         }
-        sm.mu[tid] = mu;
-        sm.isig[tid] = is;
     }
-    __syncthreads();
 
     // ---- sliding DFT in FP64: thread (segment g, bin b)
+    const int b = tid & 15;
+    const int g = tid >> 4;
+    const int s0 = g * kSegW;
+    const int segn = max(0, min(kSegW, nw - s0));
+    const double c = segn > 0 ? st[s0] : 0.0;
     {
-        const int b = tid & 15;          // bin k = b + 1
-        const int g = tid >> 4;          // segment
-        const int s0 = g * kSegW;
+        // largest |t - c| over the segment's samples, for the error bound
         double Y = 0.0;
-        if (s0 < nw) {
-            const double c = sm.mu[s0];
-            if (b < kp) {
-                const int k = b + 1;
-                double wsin, wcos;
-                sincospi(2.0 * (double)k / (double)m, &wsin, &wcos);   // omega = e^{+2 pi i k/m}
-                // direct DFT of the segment's first window by a rotating phasor
-                double xr = 0.0, xi = 0.0, pr = 1.0, pi = 0.0;
-                for (int r = 0; r < m; ++r) {
-                    double y = st[s0 + r] - c;
-                    Y = fmax(Y, fabs(y));
-                    xr = fma(y, pr, xr);
-                    xi = fma(y, pi, xi);
+        for (int r = b; r < segn + m - 1; r += 16) Y = fmax(Y, fabs(st[s0 + r] - c));
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) Y = fmax(Y, __shfl_xor(Y, off, 16));
+        if (b == 0) sm.ymax[g] = (float)(Y * (1.0 + 1e-6)) * (1.0f + 1e-6f);
+    }
+    double xr = 0.0, xi = 0.0, wcos = 1.0, wsin = 0.0;
+    const bool own = segn > 0 && b < kp;
+    if (own) {
+        const int k = b + 1;
+        sincospi(2.0 * (double)k / (double)m, &wsin, &wcos);   // omega = e^{+2 pi i k/m}
+        // X = sum_r y_r e^{-2 pi i k r/m} over four quarters, each with its
+        // own exactly started phasor
+        const int ql = (m + 3) / 4;
+        double ar[4], ai[4], pr[4], pi[4];
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const int j = (int)(((int64_t)k * (int64_t)(ch * ql)) % m);
+            double sn, cs;
+            sincospi(2.0 * (double)j / (double)m, &sn, &cs);
+            pr[ch] = cs;
+            pi[ch] = -sn;
+            ar[ch] = 0.0;
+            ai[ch] = 0.0;
+        }
+        for (int u = 0; u < ql; ++u) {
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                const int r = ch * ql + u;
+                if (r < m) {
+                    const double y = st[s0 + r] - c;
+                    ar[ch] = fma(y, pr[ch], ar[ch]);
+                    ai[ch] = fma(y, pi[ch], ai[ch]);
                     // phasor *= conj(omega)
-                    double npr = fma(pr, wcos, pi * wsin);
-                    double npi = fma(pi, wcos, -(pr * wsin));
-                    pr = npr;
-                    pi = npi;
+                    const double npr = fma(pr[ch], wcos, pi[ch] * wsin);
+                    const double npi = fma(pi[ch], wcos, -(pr[ch] * wsin));
+                    pr[ch] = npr;
+                    pi[ch] = npi;
                 }
-                for (int s = s0; s < s0 + kSegW && s < nw; ++s) {
-                    if (s > s0) {
-                        double ya = st[s - 1] - c;
-                        double yb = st[s - 1 + m] - c;
-                        Y = fmax(Y, fabs(yb));
-                        double ar = xr - ya + yb;
-                        double ai = xi;
-                        xr = fma(ar, wcos, -(ai * wsin));
-                        xi = fma(ar, wsin, ai * wcos);
+            }
+        }
+        xr = (ar[0] + ar[1]) + (ar[2] + ar[3]);
+        xi = (ai[0] + ai[1]) + (ai[2] + ai[3]);
+    }
+
+    const int row = tid >> 2;         // post-processing: four threads per row
+    const int quad = tid & 3;
+    const int pg = row / kChunk, pu = row % kChunk;
+    for (int chunk = 0; chunk < kSegW / kChunk; ++chunk) {
+        // ---- 4 slides of every (segment, bin), into the staging rows
+        for (int u = 0; u < kChunk; ++u) {
+            const int sl = chunk * kChunk + u;
+            const int s = s0 + sl;
+            FT *rw = stage[g * kChunk + u];
+            if (sl < segn) {
+                if (own) {
+                    if (sl > 0) {
+                        const double ya = st[s - 1] - c;
+                        const double yb = st[s - 1 + m] - c;
+                        const double a_r = xr - ya + yb;
+                        const double a_i = xi;
+                        xr = fma(a_r, wcos, -(a_i * wsin));
+                        xi = fma(a_r, wsin, a_i * wcos);
                     }
                     const double is = sm.isig[s];
-                    const double fr = xr * is, fi = xi * is;
-                    sm.f[s][2 * b] = (float)fr;
-                    sm.f[s][2 * b + 1] = (float)fi;
-                    if (PASS == 1 && is != 0.0) {
-                        const uint32_t slot = q.inv[L.cell_base + i0 + s];
-                        FT *rec = (FT *)q.F + (int64_t)slot * kRec;
-                        rec[2 * b] = (FT)fr;
-                        rec[2 * b + 1] = (FT)fi;
-                    }
-                }
-                if (b == 0) sm.ymax[g] = (float)(Y * (1.0 + 1e-6));
-            } else if (b < kMaxK - 1) {
-                for (int s = s0; s < s0 + kSegW && s < nw; ++s) {
-                    sm.f[s][2 * b] = 0.0f;
-                    sm.f[s][2 * b + 1] = 0.0f;
-                    if (PASS == 1 && sm.isig[s] != 0.0) {
-                        const uint32_t slot = q.inv[L.cell_base + i0 + s];
-                        FT *rec = (FT *)q.F + (int64_t)slot * kRec;
-                        rec[2 * b] = (FT)0;
-                        rec[2 * b + 1] = (FT)0;
-                    }
+                    rw[2 * b] = (FT)(xr * is);
+                    rw[2 * b + 1] = (FT)(xi * is);
+                } else if (b < kMaxK - 1) {
+                    rw[2 * b] = (FT)0;
+                    rw[2 * b + 1] = (FT)0;
                 }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // ---- per-window post-processing
-    const int w = tid;
-    bool indexed = false;
-    if (w < nw) {
-        const int64_t cell = L.cell_base + i0 + w;
-        const double is = sm.isig[w];
-        indexed = is != 0.0;     // 0 exactly for constant windows, > 0 otherwise
-        if (PASS == 0) {
-            uint64_t kw = ~0ull;
-            if (indexed) {
-                float f[2 * (kMaxK - 1)];
+        // ---- post-processing of the 64 rows
+        const int s = pg * kSegW + chunk * kChunk + pu;
+        const bool valid = s < nw;
+        const int32_t kk = valid ? sm.kpos[s] : -1;
+        const bool indexed = kk >= 0;
+        float f[kFD];
 #pragma unroll
-                for (int c = 0; c < 2 * (kMaxK - 1); ++c) f[c] = sm.f[w][c];
-                float mg[kMaxBits];
-                uint32_t sig = 0;
-                for (int b = 0; b < q.B; ++b) {
-                    float dot = 0.0f;
+        for (int x = 0; x < kFD; ++x) f[x] = (float)stage[row][x];
+        // SimHash bits (Sec. 3.4): bit l = [<g_l, F> >= 0], six per thread;
+        // margins go to LDS so that no register array is indexed at run time
+        uint32_t sig = 0;
 #pragma unroll
-                    for (int c = 0; c < 2 * (kMaxK - 1); ++c) dot = fmaf(sm.g[b][c], f[c], dot);
-                    mg[b] = fabsf(dot);
-                    if (dot >= 0.0f) sig |= 1u << (q.B - 1 - b);
-                }
-                // Hamming-1 probe order: the `probes` smallest margins among
-                // the d prefix bits, ascending (Sec. 3.4 multi-probe)
-                uint64_t order = 0;
-                uint32_t used = 0;
-                for (int h = 0; h < L.probes; ++h) {
-                    int best = -1;
-                    float bm = 0.0f;
-                    for (int b = 0; b < L.depth; ++b) {
-                        if (used & (1u << b)) continue;
-                        if (best < 0 || mg[b] < bm) { best = b; bm = mg[b]; }
-                    }
-                    used |= 1u << best;
-                    order |= (uint64_t)best << (5 * h);
-                }
-                kw = (uint64_t)sig | (order << 24);
+        for (int h = 0; h < 6; ++h) {
+            const int bt = quad * 6 + h;
+            if (bt < q.B) {
+                float dot = 0.0f;
+#pragma unroll
+                for (int x = 0; x < kFD; ++x) dot = fmaf(sm.g[bt][x], f[x], dot);
+                sm.mg[row][bt] = fabsf(dot);
+                if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
             }
-            q.keyw_nat[cell] = kw;
-        } else if (indexed) {
-            const uint32_t slot = q.inv[cell];
-            double n2 = 0.0;
-            float f[2 * (kMaxK - 1)];
+        }
+        sig |= __shfl_xor(sig, 1, kWave);
+        sig |= __shfl_xor(sig, 2, kWave);
+        // join record: orthonormal projections of the FP32 copy, FP64 dots
+        float *jr = q.jrec + (int64_t)(indexed ? kk : 0) * 8;
 #pragma unroll
-            for (int c = 0; c < 2 * (kMaxK - 1); ++c) {
-                f[c] = sm.f[w][c];
-                n2 += (double)f[c] * (double)f[c];
-            }
-            const double nrm = sqrt(n2) * (1.0 + 1e-6) + 1e-30;
-            // error bound of the stored features (see file comment)
-            const double u64 = 1.1102230246251565e-16;
-            const double ust = sizeof(FT) == 4 ? 5.9604644775390625e-08 : u64;
-            const double Y = (double)sm.ymax[w / kSegW];
-            const double Ebin = (6.0 * m * (double)m + 8.0 * kSegW * (m + 2.0) + 2.0 * m) * u64 * Y;
-            const double ecomp = sqrt(2.0 * kp) * Ebin * is * 1.001;
-            // the FP32 copy in LDS differs from the FP64 value by <= u32 |F|;
-            // that covers FP32 storage, and bounds the norm used here
-            const double estore = (ust + 4.0 * u64) * (nrm + 6e-8 * nrm) * 1.001;
-            const float e = (float)((ecomp + estore) * (1.0 + 1e-6)) * (1.0f + 2.4e-7f) + 1e-30f;
-            FT *rec = (FT *)q.F + (int64_t)slot * kRec;
-            rec[kSlotErr] = (FT)e;
-            rec[kSlotNorm] = (FT)nrm;
-            atomicMax((int *)&q.emax[l], __float_as_int(e));
-            q.keyw[slot] = q.keyw_nat[cell];
-            // join record: orthonormal projections of the FP32 copy, FP64 dots
-            float *jr = q.jrec + (int64_t)slot * 8;
-#pragma unroll
-            for (int d = 0; d < kJoinDims; ++d) {
+        for (int dd = 0; dd < 2; ++dd) {
+            const int dim = quad + 4 * dd;
+            if (dim < kJoinDims && indexed) {
                 double p = 0.0;
 #pragma unroll
-                for (int c = 0; c < 2 * (kMaxK - 1); ++c)
-                    p = fma(q.ujoin[d * 2 * (kMaxK - 1) + c], (double)f[c], p);
-                jr[d] = (float)p;
+                for (int x = 0; x < kFD; ++x) p = fma(q.ujoin[dim * kFD + x], (double)f[x], p);
+                jr[dim] = (float)p;
             }
-            jr[6] = __uint_as_float(slot);
+        }
+        // norm of the FP32 copy, across the quad
+        double n2 = 0.0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const int xx = quad * 8 + x;
+            if (xx < kFD) n2 += (double)f[xx] * (double)f[xx];
+        }
+        n2 += __shfl_xor(n2, 1, kWave);
+        n2 += __shfl_xor(n2, 2, kWave);
+        __syncthreads();                      // margins visible to the quad leader
+        if (indexed && quad == 0) {
+            // Hamming-1 probe order: the `probes` smallest margins among the
+            // d prefix bits, ascending (Sec. 3.4 multi-probe)
+            uint64_t order = 0;
+            uint32_t used = 0;
+            for (int h = 0; h < L.probes; ++h) {
+                int best = -1;
+                float bm = 0.0f;
+                for (int bt = 0; bt < L.depth; ++bt) {
+                    if (used & (1u << bt)) continue;
+                    const float v = sm.mg[row][bt];
+                    if (best < 0 || v < bm) { best = bt; bm = v; }
+                }
+                used |= 1u << best;
+                order |= (uint64_t)best << (5 * h);
+            }
+            q.keyw[kk] = (uint64_t)sig | (order << 24);
+            const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
+            q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
+            q.sval[kk] = (uint32_t)kk;
+            jr[6] = __uint_as_float((uint32_t)kk);
             jr[7] = 0.0f;
+            // error bound of the stored features (see file comment): direct
+            // start (4 quarters) + 63 slides in FP64, the multiplication by
+            // 1/sigma, and the rounding to FT; the FP32 copy differs from the
+            // FP64 value by <= u32 |F|, which also bounds the norm used here
+            const double nrm = sqrt(n2) * (1.0 + 1e-6) + 1e-30;
+            const double u64 = 1.1102230246251565e-16;
+            const double ust = sizeof(FT) == 4 ? 5.9604644775390625e-08 : u64;
+            const double Y = (double)sm.ymax[pg];
+            const double Ebin = (6.0 * m * (double)m + 8.0 * kSegW * (m + 2.0) + 2.0 * m) * u64 * Y;
+            const double ecomp = sqrt(2.0 * kp) * Ebin * sm.isig[s] * 1.001;
+            const double estore = (ust + 4.0 * u64) * (nrm + 6e-8 * nrm) * 1.001;
+            const float e = (float)((ecomp + estore) * (1.0 + 1e-6)) * (1.0f + 2.4e-7f) + 1e-30f;
+            stage[row][kSlotErr] = (FT)e;
+            stage[row][kSlotNorm] = (FT)nrm;
+            atomicMax(&sm.emax, __float_as_int(e));
         }
-    }
-    if (PASS == 0) {
-        uint64_t bal = __ballot(indexed);
-        if (lane_id() == 0) sm.wcount[tid / kWave] = (uint32_t)__popcll(bal);
         __syncthreads();
-        if (tid == 0) {
-            uint32_t s = 0;
-            for (int k = 0; k < kBlock / kWave; ++k) s += sm.wcount[k];
-            tile_cnt[tile] = s;
+        // ---- whole records out, 16 bytes per thread and store
+        constexpr int kPer = 16 / (int)sizeof(FT);           // FT values per 16 bytes
+        constexpr int kParts = kRec / kPer;                  // 16-byte parts per record
+        for (int flat = tid; flat < kRows * kParts; flat += kBlock) {
+            const int r = flat / kParts, part = flat % kParts;
+            const int sr = (r / kChunk) * kSegW + chunk * kChunk + (r % kChunk);
+            if (sr < nw) {
+                const int32_t kr = sm.kpos[sr];
+                if (kr >= 0) {
+                    const FT *src = &stage[r][part * kPer];
+                    FT *dst = (FT *)q.F + (int64_t)kr * kRec + part * kPer;
+                    if (sizeof(FT) == 8) {
+                        double2 v;
+                        v.x = (double)src[0];
+                        v.y = (double)src[1];
+                        *(double2 *)dst = v;
+                    } else {
+                        float4 v;
+                        v.x = (float)src[0];
+                        v.y = (float)src[1];
+                        v.z = (float)src[kPer > 2 ? 2 : 0];
+                        v.w = (float)src[kPer > 3 ? 3 : 0];
+                        *(float4 *)dst = v;
+                    }
+                }
+            }
         }
+        __syncthreads();
     }
+    if (tid == 0 && sm.emax) atomicMax((int *)&q.emax[l], sm.emax);
 }
 
-// Sort input in (length, start) order: key = len << key_shift | prefix <<
-// (key_shift - d), value = cell.  Also counts bucket populations.
-__global__ __launch_bounds__(kBlock) void k_emit_sortin(Req q, const uint32_t *__restrict__ tile_off) {
-    __shared__ uint32_t wc[kBlock / kWave];
-    const int64_t tile = blockIdx.x;
-    const int l = find_tile_len(q.len, q.L, tile);
-    const LenInfo L = q.len[l];
-    const int64_t i0 = (tile - L.tile_base) * kTileW;
-    const int nw = (int)min<int64_t>(kTileW, L.W - i0);
-    const int tid = threadIdx.x;
-    uint64_t kw = ~0ull;
-    const int64_t cell = L.cell_base + i0 + tid;
-    if (tid < nw) kw = q.keyw_nat[cell];
-    const bool ix = kw != ~0ull;
-    const uint64_t bal = __ballot(ix);
-    if (lane_id() == 0) wc[tid / kWave] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    if (ix) {
-        uint32_t pos = tile_off[tile] + (uint32_t)__popcll(bal & lanemask_lt());
-        for (int k = 0; k < tid / kWave; ++k) pos += wc[k];
-        const uint32_t sig = (uint32_t)(kw & 0xFFFFFFu);
-        const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
-        q.skey[pos] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
-        q.sval[pos] = (uint32_t)cell;
-        atomicAdd(&q.bucket_cnt[L.bucket_base + prefix], 1u);
-    }
+// First slot of every bucket from the sorted keys: between two consecutive
+// sorted entries, every bucket index in (previous, current] starts at the
+// current slot (empty buckets included); the entry past the end closes the
+// last buckets.
+__global__ __launch_bounds__(kBlock) void k_bucket_bounds(Req q, int64_t N, int64_t nbuckets,
+                                                          uint32_t *__restrict__ bstart) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s > N) return;
+    const uint32_t mask = (1u << q.key_shift) - 1u;
+    auto gidx = [&](uint32_t key) -> int64_t {
+        const int l = (int)(key >> q.key_shift);
+        const int d = q.len[l].depth;
+        return q.len[l].bucket_base + (int64_t)((key & mask) >> (q.key_shift - d));
+    };
+    const int64_t cur = s < N ? gidx(q.skey[s]) : nbuckets;
+    const int64_t prev = s > 0 ? gidx(q.skey[s - 1]) : -1;
+    for (int64_t b = prev + 1; b <= cur; ++b) bstart[b] = (uint32_t)s;
+}
+
+// Slot maps after the sort: k -> slot and slot -> cell.
+__global__ __launch_bounds__(kBlock) void k_slot_maps(Req q, int64_t N) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    const uint32_t k = q.perm[s];
+    q.inv[k] = (uint32_t)s;
+    q.pcell[s] = q.cell[k];
 }
 
 __global__ __launch_bounds__(kBlock) void k_invert(const uint32_t *__restrict__ perm, int64_t N,
@@ -342,31 +432,37 @@ void launch_changepoints(const double *t, int64_t n, uint32_t *flag, int *bad, h
     hipLaunchKernelGGL(k_changepoints, dim3(nblk(n + 1)), dim3(kBlock), 0, s, t, n, flag, bad);
 }
 
-void launch_count_index(const LenInfo *len, int L, const uint32_t *E, unsigned long long *cnt,
-                        int64_t maxW, hipStream_t s) {
-    int64_t bx = (maxW + kBlock * 8 - 1) / (kBlock * 8);
-    if (bx < 1) bx = 1;
-    if (bx > 4096) bx = 4096;
-    hipLaunchKernelGGL(k_count_index, dim3((unsigned)bx, (unsigned)L), dim3(kBlock), 0, s, len, E,
-                       cnt);
+void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t ntiles,
+                        uint32_t *tile_cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)ntiles), dim3(kBlock), 0, s, len, L, E,
+                       tile_cnt);
 }
 
-void launch_sketch(int pass, int precision, const Req &q, const uint32_t *E, uint32_t *tile_cnt,
+void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                    int64_t ntiles, int max_m, hipStream_t s) {
-    const size_t dyn = (size_t)(kTileW + max_m) * sizeof(double);
-    if (pass == 0)
-        hipLaunchKernelGGL((k_sketch<0, float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_cnt);
-    else if (precision == 0)
-        hipLaunchKernelGGL((k_sketch<1, double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_cnt);
-    else
-        hipLaunchKernelGGL((k_sketch<1, float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_cnt);
+    // samples (1024 + m - 1 doubles) then the staging rows, sized for the
+    // longest window of the request
+    if (precision == 0) {
+        const size_t dyn = (size_t)(kTileW + max_m) * sizeof(double) +
+                           (size_t)kSegs * kChunk * (kRec + 1) * sizeof(double);
+        hipLaunchKernelGGL((k_sketch<double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                           tile_off);
+    } else {
+        const size_t dyn = (size_t)(kTileW + max_m) * sizeof(double) +
+                           (size_t)kSegs * kChunk * (kRec + 1) * sizeof(float);
+        hipLaunchKernelGGL((k_sketch<float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                           tile_off);
+    }
 }
 
-void launch_emit_sortin(const Req &q, const uint32_t *tile_off, int64_t ntiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit_sortin, dim3((unsigned)ntiles), dim3(kBlock), 0, s, q, tile_off);
+void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(nblk(N + 1)), dim3(kBlock), 0, s, q, N, nbuckets,
+                       bstart);
+}
+
+void launch_slot_maps(const Req &q, int64_t N, hipStream_t s) {
+    if (N > 0) hipLaunchKernelGGL(k_slot_maps, dim3(nblk(N)), dim3(kBlock), 0, s, q, N);
 }
 
 void launch_invert(const uint32_t *perm, int64_t N, uint32_t *inv, hipStream_t s) {

@@ -17,22 +17,26 @@ constexpr int    kSlotNorm   = 31;        // record slot of ||F||
 constexpr int    kMaxBits    = 24;        // SimHash bits B (Sec. 4: B = 24)
 constexpr int    kProbeSlots = 8;         // Hamming-1 probes kept per key word
 constexpr int    kJoinDims   = 6;         // orthonormal projections of a join record
-constexpr int    kMaxM       = 4096;      // longest window supported
-constexpr int    kTileW      = 256;       // windows per sketch tile
-constexpr int    kSegW       = 16;        // windows per sliding-DFT segment
+constexpr int    kMaxM       = 2048;      // longest window supported
+constexpr int    kTileW      = 1024;      // windows per sketch tile
+constexpr int    kSegW       = 64;        // windows per sliding-DFT segment
+constexpr int    kSegs       = kTileW / kSegW;   // 16 segments, one per 16 lanes
+constexpr int    kChunk      = 4;         // slides between two post-processing steps
 constexpr double kEps0       = 1e-6;      // zero snap (Sec. 3.6)
 constexpr uint64_t kInfBits  = 0x7FF0000000000000ull;   // +inf as FP64 bits
 
-// Per-length metadata, device resident.
+// Per-length metadata, device resident.  Every per-window array is indexed
+// by the compacted position k of the non-constant ("indexed") windows in
+// (length, start) order; the windows of length l are k in [kbase, kbase + n_index).
 struct LenInfo {
     int32_t m;            // window length
     int32_t kprime;       // K' = min(K-1, ceil(m/2)-1)
     int32_t depth;        // directory depth d (Prop. 4 final state)
     int32_t probes;       // Hamming-1 probes h = min(cap, d, 1 + max(0, d - d0))
     int64_t W;            // windows n - m + 1
-    int64_t cell_base;    // first cell of this length in natural order
-    int64_t slot_base;    // first slot of this length in bucket order
-    int64_t bucket_base;  // first bucket counter of this length
+    int64_t cell_base;    // first cell of this length in (length, start) order
+    int64_t kbase;        // first indexed position of this length
+    int64_t bucket_base;  // first bucket of this length
     int64_t n_index;      // non-constant windows (entries of the directory)
     int64_t tile_base;    // first sketch tile of this length
 };
@@ -50,21 +54,22 @@ struct Req {
     int32_t jkey_shift;    // join key: len_idx << jkey_shift | quantized p1
     int32_t precision;
     const LenInfo *len;    // [L]
-    const int32_t *cpre;   // [n] inclusive prefix count of change points
-    double  *mu;           // [cells] window mean
-    double  *isig;         // [cells] 1 / sigma (population standard deviation)
-    uint64_t *P;           // [cells] profile, FP64 bits (atomicMin)
-    uint64_t *keyw_nat;    // [cells] key word (natural order), pass A
-    uint32_t *skey;        // [N] sort keys (bucket)       -- sort buffers
-    uint32_t *sval;        // [N] sort values (cell id)
-    uint32_t *bucket_cnt;  // [buckets] population, then start slot (scan)
-    uint32_t *perm;        // [N] slot -> cell
-    uint32_t *inv;         // [cells] cell -> slot (valid for indexed cells)
-    void    *F;            // [N][kRec] features in slot order (float or double)
-    uint64_t *keyw;        // [N] key words in slot order
+    // per indexed window k, in (length, start) order
+    uint32_t *cell;        // [N] cell id (cell_base of its length + start)
+    double  *mu;           // [N] window mean
+    double  *isig;         // [N] 1 / sigma (population standard deviation)
+    uint64_t *P;           // [N] profile, FP64 bits (atomicMin)
+    void    *F;            // [N][kRec] features (float or double)
+    uint64_t *keyw;        // [N] key word: signature | probe order << 24
+    float   *jrec;         // [N][8] join record: p1..p6, k bits, 0
+    // bucket order (slots)
+    uint32_t *skey;        // [N] sort keys
+    uint32_t *sval;        // [N] sort values (k)
+    uint32_t *perm;        // [N] slot -> k
+    uint32_t *pcell;       // [N] slot -> cell
+    uint32_t *inv;         // [N] k -> slot
     const float *gproj;    // [L][B][30] SimHash projections
     const double *ujoin;   // [kJoinDims][30] orthonormal join directions
-    float   *jrec;         // [N][8] join record in slot order: p1..p6, slot bits
     float   *emax;         // [L] largest e_i of each length
     unsigned long long *counters;   // stats counters
     int     *bad;          // raised on inputs the library cannot represent
@@ -102,55 +107,14 @@ __device__ __forceinline__ int find_len(const LenInfo *len, int L, int64_t cell)
     return lo;
 }
 
-__device__ __forceinline__ int find_len_slot(const LenInfo *len, int L, int64_t slot) {
+// Length index of an indexed position k (slots share the per-length ranges).
+__device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) {
     int lo = 0, hi = L - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (len[mid].slot_base <= slot) lo = mid; else hi = mid - 1;
+        if (len[mid].kbase <= k) lo = mid; else hi = mid - 1;
     }
     return lo;
-}
-
-// Exact z-normalized distance between windows a and b of length m, FP64,
-// r ascending, z = (t - mu) * (1/sigma) per sample (Sec. 2).  Symmetric bit
-// for bit in (a, b): only squares of differences are summed.
-// Contraction is off so that every kernel rounds this function the same way:
-// the profile, the join and the exact rows must agree bit for bit.
-__device__ __forceinline__ double zdist(const double *__restrict__ t, int64_t a, double mua,
-                                        double ia, int64_t b, double mub, double ib, int m) {
-#pragma clang fp contract(off)
-    double acc = 0.0;
-    for (int r = 0; r < m; ++r) {
-        double za = (t[a + r] - mua) * ia;
-        double zb = (t[b + r] - mub) * ib;
-        double e = za - zb;
-        acc = fma(e, e, acc);
-    }
-    return sqrt(acc);
-}
-
-// Certified lower bound on d_m(q, c) from the stored features: the Parseval
-// bound (Lemma 2) of the true features is at least
-//   sqrt(2/m) (||F~q - F~c|| - e_q - e_c),
-// and every rounding of this evaluation is absorbed by the relative slacks.
-template <typename FT>
-__device__ __forceinline__ float lb_safe(const FT *__restrict__ fq, const FT *__restrict__ fc,
-                                         int kp, float sqrt2m) {
-    FT acc = 0;
-    for (int c = 0; c < 2 * kp; ++c) {
-        FT e = fq[c] - fc[c];
-        acc = fma(e, e, acc);
-    }
-    const FT nd = sqrt(acc);
-    const FT es = fq[kSlotErr] + fc[kSlotErr];
-    if (sizeof(FT) == 4) {
-        float v = (float)nd * (1.0f - 1e-5f) - (float)es * (1.0f + 1e-5f);
-        return v > 0.0f ? v * sqrt2m * (1.0f - 1e-6f) : 0.0f;
-    } else {
-        double v = (double)nd * (1.0 - 1e-12) - (double)es * (1.0 + 1e-12);
-        // the float result is rounded down
-        return v > 0.0 ? __double2float_rd(v * (double)sqrt2m * (1.0 - 1e-6)) : 0.0f;
-    }
 }
 
 struct JoinLen {
@@ -163,9 +127,122 @@ struct JoinLen {
 struct RowReq {
     int32_t l;          // length index
     int32_t pad;
-    int64_t i;          // start of the cell
+    int64_t k;          // indexed position of the cell
     uint64_t target;    // pass 2: FP64 bits of the value whose smallest j is wanted
 };
+
+// The canonical exact distance, computed by a group of 16 consecutive lanes
+// (four groups per wavefront, each with its own pair): lane g of the group
+// sums the terms r = g, g+16, g+32, ... in ascending order, then a butterfly
+// over the 16 lanes adds the partial sums.  Every kernel that writes,
+// compares or reports a distance calls this function, so they all agree bit
+// for bit; every step is symmetric in (a, b), so d(a, b) == d(b, a).  Loads
+// of a group are contiguous.  All 64 lanes of the wavefront must call it.
+constexpr int kGroup = 16;
+
+__device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
+                                              double ia, int64_t b, double mub, double ib, int m) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    for (int r = lane_id() & (kGroup - 1); r < m; r += kGroup) {
+        const double za = (t[a + r] - mua) * ia;
+        const double zb = (t[b + r] - mub) * ib;
+        const double e = za - zb;
+        acc = fma(e, e, acc);
+    }
+#pragma unroll
+    for (int off = 1; off < kGroup; off <<= 1) acc += __shfl_xor(acc, off, kGroup);
+    return sqrt(acc);
+}
+
+// Certified lower bound on d_m(q, c) from two stored feature records: the
+// Parseval bound (Lemma 2) of the true features is at least
+//   sqrt(2/m) (||F~q - F~c|| - e_q - e_c),
+// and every rounding of this evaluation is absorbed by the relative slacks
+// (applied to the norm before the subtraction, so the result never exceeds
+// the true bound even when the two terms nearly cancel).  All 30 slots are
+// used: slots beyond 2K' are zero on both sides and add nothing.
+template <typename FT>
+__device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__restrict__ fc,
+                                        float sqrt2m) {
+    FT acc = 0;
+    if (sizeof(FT) == 8) {
+        const double2 *a = (const double2 *)fq;
+        const double2 *b = (const double2 *)fc;
+#pragma unroll
+        for (int x = 0; x < kMaxK - 1; ++x) {
+            const double2 u = a[x], v = b[x];
+            const double e0 = u.x - v.x, e1 = u.y - v.y;
+            acc = fma(e0, e0, acc);
+            acc = fma(e1, e1, acc);
+        }
+    } else {
+        const float4 *a = (const float4 *)fq;
+        const float4 *b = (const float4 *)fc;
+#pragma unroll
+        for (int x = 0; x < 7; ++x) {
+            const float4 u = a[x], v = b[x];
+            const float e0 = u.x - v.x, e1 = u.y - v.y, e2 = u.z - v.z, e3 = u.w - v.w;
+            acc = fmaf(e0, e0, acc);
+            acc = fmaf(e1, e1, acc);
+            acc = fmaf(e2, e2, acc);
+            acc = fmaf(e3, e3, acc);
+        }
+        const float2 u = ((const float2 *)fq)[14], v = ((const float2 *)fc)[14];
+        const float e0 = u.x - v.x, e1 = u.y - v.y;
+        acc = fmaf(e0, e0, acc);
+        acc = fmaf(e1, e1, acc);
+    }
+    const FT nd = sqrt(acc);
+    const FT es = fq[kSlotErr] + fc[kSlotErr];
+    if (sizeof(FT) == 4) {
+        float v = (float)nd * (1.0f - 1e-5f) - (float)es * (1.0f + 1e-5f);
+        return v > 0.0f ? v * sqrt2m * (1.0f - 1e-6f) : 0.0f;
+    } else {
+        double v = (double)nd * (1.0 - 1e-12) - (double)es * (1.0 + 1e-12);
+        return v > 0.0 ? __double2float_rd(v * (double)sqrt2m * (1.0 - 1e-6)) : 0.0f;
+    }
+}
+
+// Verification of the proposals of a wavefront.  Every lane whose bit is set
+// in `mask` has a proposal (a, b: window starts; mua, ia, mub, ib: moments;
+// m).  The proposals are taken four at a time, one per 16-lane group;
+// `on_result(d)` runs on the proposing lane with its snapped distance.
+template <typename F>
+__device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__restrict__ t,
+                                                 int64_t a, double mua, double ia, int64_t b,
+                                                 double mub, double ib, int m, F &&on_result) {
+    const int lane = lane_id();
+    const int grp = lane / kGroup;
+    while (mask) {
+        // the next four proposing lanes, in lane order
+        int src[4];
+        int cnt = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            src[g] = -1;
+            if (mask) {
+                src[g] = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                ++cnt;
+            }
+        }
+        const int my = src[grp] < 0 ? src[0] : src[grp];
+        const int64_t ga = __shfl(a, my, kWave);
+        const int64_t gb = __shfl(b, my, kWave);
+        const double gmua = __shfl(mua, my, kWave), gia = __shfl(ia, my, kWave);
+        const double gmub = __shfl(mub, my, kWave), gib = __shfl(ib, my, kWave);
+        int gm = __shfl(m, my, kWave);
+        if (src[grp] < 0) gm = 0;
+        const double d = snap(group_zdist(t, ga, gmua, gia, gb, gmub, gib, gm));
+        // hand each result back to its proposing lane
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const double dg = __shfl(d, g * kGroup, kWave);
+            if (g < cnt && lane == src[g]) on_result(dg);
+        }
+    }
+}
 
 // --------------------------------------------------- host-side launchers
 // (k_scan.hip)
@@ -181,11 +258,13 @@ void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
 
 // (k_sketch.hip)
 void launch_changepoints(const double *t, int64_t n, uint32_t *flag, int *bad, hipStream_t s);
-void launch_count_index(const LenInfo *len, int L, const uint32_t *E, unsigned long long *cnt,
-                        int64_t maxW, hipStream_t s);
-void launch_sketch(int pass, int precision, const Req &q, const uint32_t *E, uint32_t *tile_cnt,
+void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t ntiles,
+                        uint32_t *tile_cnt, hipStream_t s);
+void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                    int64_t ntiles, int max_m, hipStream_t s);
-void launch_emit_sortin(const Req &q, const uint32_t *tile_off, int64_t ntiles, hipStream_t s);
+void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
+                          hipStream_t s);
+void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);
 void launch_invert(const uint32_t *perm, int64_t N, uint32_t *inv, hipStream_t s);
 // (k_probe.hip)
 void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, hipStream_t s);
@@ -204,10 +283,15 @@ void launch_join_keys(const Req &q, const float *prange, int64_t N, uint32_t *jk
                       hipStream_t s);
 void launch_join_gather(const float *jrec, const uint32_t *jperm, int64_t N, float *jsorted,
                         hipStream_t s);
+void launch_join_queries(const Req &q, const uint32_t *jinv, int64_t N, uint32_t *jq,
+                         uint32_t *count, hipStream_t s);
 void launch_join(int precision, const Req &q, const float *js, const uint32_t *jkey,
-                 const JoinLen *jl, int64_t N, double T, hipStream_t s);
-void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxW, int find_min,
+                 const JoinLen *jl, const uint32_t *jq, int64_t nq, int64_t N, double T,
+                 hipStream_t s);
+void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,
+                       hipStream_t s);
 
 }  // namespace pmp

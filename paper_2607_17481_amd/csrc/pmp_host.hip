@@ -293,14 +293,14 @@ static void plan_lengths(Plan &p, int64_t n, int m_min, int m_max, int step) {
     while ((1 << p.len_bits) < p.L) ++p.len_bits;
 }
 
-// depths, probes, bases from the index counts
-static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, int alpha) {
+// depths, probes and bases from the per-length index counts
+static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, int alpha, int K) {
     const int dcap = std::min(o.B, 32 - p.len_bits - 1);
-    int64_t sb = 0, bb = 0;
+    int64_t kb = 0, bb = 0;
     p.max_depth = 0;
     for (int l = 0; l < p.L; ++l) {
         LenInfo &L = p.len[l];
-        L.kprime = 0;
+        L.kprime = kprime_of(K, L.m);
         L.n_index = cnt[l];
         int d = 0;
         while (d < dcap && L.n_index > (int64_t)alpha << d) ++d;   // Prop. 4 final depth
@@ -308,102 +308,102 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
         int h = d > 0 ? 1 + std::max(0, d - o.d0) : 0;
         h = std::min(h, std::min(d, o.probe_cap));
         L.probes = h;
-        L.slot_base = sb;
+        L.kbase = kb;
         L.bucket_base = bb;
-        sb += L.n_index;
+        kb += L.n_index;
         bb += (int64_t)1 << d;
         p.max_depth = std::max(p.max_depth, d);
     }
-    p.N = sb;
+    p.N = kb;
     p.nbuckets = bb;
     p.key_shift = p.max_depth;
     p.jkey_shift = 32 - p.len_bits - 1;
 }
 
 struct Bufs {
-    // phase 1
+    // phase 1: sized by the series and the lengths
     LenInfo *len;
-    uint32_t *flags, *E, *scan_tmp;
+    uint32_t *flags, *E, *scan_tmp, *tile_off;
     int *bad;
-    unsigned long long *counts, *counters;
-    float *emax, *gproj;
+    unsigned long long *counters;
+    float *emax, *gproj, *prange;
     double *ujoin;
     unsigned int *hist;
-    uint32_t *nless;
-    double *mu, *isig;
-    uint64_t *P, *keyw_nat;
-    uint32_t *tile_cnt, *inv;
-    uint32_t *sel_cnt;
-    uint32_t *less_cell, *eq;
-    uint64_t *less_val;
+    uint32_t *nless, *jq_count;
     RowReq *rows;
     unsigned long long *row_min, *row_arg;
     int64_t *cal_starts;
     double *cal_win;
-    // phase 2
-    uint32_t *skey, *sval, *skey2, *sval2;
-    void *sort_tmp;
-    uint32_t *bstart;
-    void *F;
-    uint64_t *keyw;
-    float *jrec, *jsorted, *prange;
-    uint32_t *jk, *jv, *jk2, *jv2;
     JoinLen *jl;
+    // phase 2: sized by the indexed windows N
+    uint32_t *cell;
+    double *mu, *isig;
+    uint64_t *P, *keyw;
+    void *F;
+    float *jrec, *jsorted;
+    uint32_t *skey, *sval, *skey2, *sval2, *pcell, *inv, *bstart;
+    void *sort_tmp;
+    uint32_t *jk, *jv, *jk2, *jv2, *jinv, *jq;
+    uint32_t *sel_cnt, *less_k, *eq_k, *sel_cell;
+    uint64_t *less_val;
 };
 
 static int64_t need_select(int k, int m_max) { return (int64_t)k * (m_max + 1); }
 
 static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
-    const int64_t nsel = select_blocks(p.cells) + 1;
-    const int64_t need = need_select(k, p.max_m);
     b.len = take<LenInfo>(a, p.L);
     b.flags = take<uint32_t>(a, p.n + 1);
     b.E = take<uint32_t>(a, p.n + 1);
+    b.tile_off = take<uint32_t>(a, p.ntiles + 1);
     b.scan_tmp = (uint32_t *)a.take(scan_temp_bytes(std::max<int64_t>(
-        {p.n + 1, p.ntiles + 1, p.cells, nsel, (int64_t)1 << 26})));
+        {p.n + 1, p.ntiles + 1, select_blocks(p.cells) + 1, p.cells})));
     b.bad = take<int>(a, 1);
-    b.counts = take<unsigned long long>(a, p.L);
     b.counters = take<unsigned long long>(a, C_NCOUNTERS);
     b.emax = take<float>(a, p.L);
     b.gproj = take<float>(a, (int64_t)p.L * kMaxBits * kFD);
+    b.prange = take<float>(a, p.L);
     b.ujoin = take<double>(a, kJoinDims * kFD);
     b.hist = take<unsigned int>(a, 2048);
     b.nless = take<uint32_t>(a, 1);
-    b.mu = take<double>(a, p.cells);
-    b.isig = take<double>(a, p.cells);
-    b.P = take<uint64_t>(a, p.cells);
-    b.keyw_nat = take<uint64_t>(a, p.cells);
-    b.tile_cnt = take<uint32_t>(a, p.ntiles + 1);
-    b.inv = take<uint32_t>(a, p.cells);
-    b.sel_cnt = take<uint32_t>(a, nsel);
-    b.less_cell = take<uint32_t>(a, need);
-    b.less_val = take<uint64_t>(a, need);
-    b.eq = take<uint32_t>(a, need);
+    b.jq_count = take<uint32_t>(a, 1);
     b.rows = take<RowReq>(a, k);
     b.row_min = take<unsigned long long>(a, k);
     b.row_arg = take<unsigned long long>(a, k);
     b.cal_starts = take<int64_t>(a, 3 * 256);
     b.cal_win = take<double>(a, (int64_t)3 * 256 * p.max_m);
+    b.jl = take<JoinLen>(a, p.L);
 }
 
-static void carve2(Arena &a, Bufs &b, const Plan &p, int precision) {
-    const int64_t N = p.N;
+static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
+    const int64_t N = std::max<int64_t>(p.N, 1);
+    const int64_t need = need_select(k, p.max_m);
+    b.cell = take<uint32_t>(a, N);
+    b.mu = take<double>(a, N);
+    b.isig = take<double>(a, N);
+    b.P = take<uint64_t>(a, N);
+    b.keyw = take<uint64_t>(a, N);
+    b.F = a.take((size_t)N * kRec * (precision == 0 ? 8 : 4));
+    b.jrec = take<float>(a, N * 8);
+    b.jsorted = take<float>(a, N * 8);
     b.skey = take<uint32_t>(a, N);
     b.sval = take<uint32_t>(a, N);
     b.skey2 = take<uint32_t>(a, N);
     b.sval2 = take<uint32_t>(a, N);
-    b.sort_tmp = a.take(sort_temp_bytes(std::max<int64_t>(N, 1)));
+    b.pcell = take<uint32_t>(a, N);
+    b.inv = take<uint32_t>(a, N);
     b.bstart = take<uint32_t>(a, p.nbuckets + 1);
-    b.F = a.take((size_t)std::max<int64_t>(N, 1) * kRec * (precision == 0 ? 8 : 4));
-    b.keyw = take<uint64_t>(a, N);
-    b.jrec = take<float>(a, N * 8);
-    b.jsorted = take<float>(a, N * 8);
+    b.sort_tmp = a.take(sort_temp_bytes(N));
     b.jk = take<uint32_t>(a, N);
     b.jv = take<uint32_t>(a, N);
     b.jk2 = take<uint32_t>(a, N);
     b.jv2 = take<uint32_t>(a, N);
-    b.prange = take<float>(a, p.L);
-    b.jl = take<JoinLen>(a, p.L);
+    b.jinv = take<uint32_t>(a, N);
+    b.jq = take<uint32_t>(a, N);
+    b.sel_cnt = take<uint32_t>(a, select_blocks(N) + 1);
+    b.less_k = take<uint32_t>(a, need);
+    b.less_val = take<uint64_t>(a, need);
+    b.eq_k = take<uint32_t>(a, need);
+    b.sel_cell = take<uint32_t>(a, 2 * need);
 }
 
 // ------------------------------------------------------------ selection
@@ -412,6 +412,7 @@ struct Cand {
     double d;
     int l;
     int64_t i;
+    uint32_t k;
 };
 
 static bool cand_less(const Cand &a, const Cand &b, const Plan &p) {
@@ -430,10 +431,12 @@ static int len_of_cell(const Plan &p, int64_t cell) {
 }
 
 // The first `need` cells of the (P, m, i) order, sorted, then the greedy of
-// Sec. 2 over them.  Returns the accepted cells.
-static int select_topk(const Plan &p, Bufs &b, const uint64_t *dP, int k, hipStream_t s,
-                       std::vector<Cand> &accepted) {
+// Sec. 2 over them.  P is indexed by k, whose order is the (m, i) order of the
+// non-constant windows; constant windows have no cell value.
+static int select_topk(const Plan &p, Bufs &b, int k, hipStream_t s, std::vector<Cand> &accepted) {
     accepted.clear();
+    const uint64_t *dP = b.P;
+    const int64_t N = p.N;
     const int64_t need_all = need_select(k, p.max_m);
     const int shifts[6] = {53, 42, 31, 20, 9, 0};
     const int widths[6] = {11, 11, 11, 11, 11, 9};
@@ -442,9 +445,9 @@ static int select_topk(const Plan &p, Bufs &b, const uint64_t *dP, int k, hipStr
     uint64_t pivot = kInfBits;
     int64_t need_eq = 0;
     std::vector<unsigned int> h(2048);
-    for (int ps = 0; ps < 6; ++ps) {
+    for (int ps = 0; ps < 6 && N > 0; ++ps) {
         HIPCHK(hipMemsetAsync(b.hist, 0, 2048 * sizeof(unsigned int), s));
-        launch_select_hist(dP, p.cells, shifts[ps], widths[ps], high, b.hist, s);
+        launch_select_hist(dP, N, shifts[ps], widths[ps], high, b.hist, s);
         HIPCHK(hipMemcpyAsync(h.data(), b.hist, (1 << widths[ps]) * sizeof(unsigned int),
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -473,41 +476,47 @@ static int select_topk(const Plan &p, Bufs &b, const uint64_t *dP, int k, hipStr
             need_eq = remaining;
         }
     }
+    if (N == 0) return PMP_OK;
     // ordered compaction
-    const int64_t nsb = select_blocks(p.cells);
-    launch_select_count(dP, p.cells, pivot, b.sel_cnt, s);
+    const int64_t nsb = select_blocks(N);
+    launch_select_count(dP, N, pivot, b.sel_cnt, s);
     scan_exclusive_u32(b.sel_cnt, b.sel_cnt, nsb, nullptr, b.scan_tmp, s);
     HIPCHK(hipMemsetAsync(b.nless, 0, sizeof(uint32_t), s));
-    launch_select_emit(dP, p.cells, pivot, (uint32_t)need_eq, b.sel_cnt, b.less_cell, b.less_val,
-                       b.nless, (uint32_t)need_all, b.eq, s);
+    launch_select_emit(dP, N, pivot, (uint32_t)need_eq, b.sel_cnt, b.less_k, b.less_val, b.nless,
+                       (uint32_t)need_all, b.eq_k, s);
     uint32_t nless = 0;
     HIPCHK(hipMemcpyAsync(&nless, b.nless, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (nless > (uint32_t)need_all) return fail(PMP_EINTERNAL, "selection overflow");
-    std::vector<uint32_t> lc(nless), ec(need_eq);
-    if (nless)
-        HIPCHK(hipMemcpyAsync(lc.data(), b.less_cell, nless * sizeof(uint32_t),
-                              hipMemcpyDeviceToHost, s));
-    if (need_eq)
-        HIPCHK(hipMemcpyAsync(ec.data(), b.eq, need_eq * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // cells of the selected positions
+    launch_gather_u32(b.cell, b.less_k, nless, b.sel_cell, s);
+    launch_gather_u32(b.cell, b.eq_k, need_eq, b.sel_cell + need_all, s);
+    std::vector<uint32_t> lk(nless), ek(need_eq), lc(nless), ec(need_eq);
     std::vector<uint64_t> lv(nless);
-    if (nless)
-        HIPCHK(hipMemcpyAsync(lv.data(), b.less_val, nless * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    if (nless) {
+        HIPCHK(hipMemcpyAsync(lk.data(), b.less_k, nless * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(lv.data(), b.less_val, nless * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(lc.data(), b.sel_cell, nless * 4, hipMemcpyDeviceToHost, s));
+    }
+    if (need_eq) {
+        HIPCHK(hipMemcpyAsync(ek.data(), b.eq_k, need_eq * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ec.data(), b.sel_cell + need_all, need_eq * 4, hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     std::vector<Cand> c;
     c.reserve(nless + need_eq);
     for (uint32_t x = 0; x < nless; ++x) {
         double d;
         memcpy(&d, &lv[x], 8);
-        int l = len_of_cell(p, lc[x]);
-        c.push_back({d, l, (int64_t)lc[x] - p.len[l].cell_base});
+        const int l = len_of_cell(p, lc[x]);
+        c.push_back({d, l, (int64_t)lc[x] - p.len[l].cell_base, lk[x]});
     }
     std::sort(c.begin(), c.end(), [&](const Cand &a, const Cand &bb) { return cand_less(a, bb, p); });
     double pv;
     memcpy(&pv, &pivot, 8);
     for (int64_t x = 0; x < need_eq; ++x) {
-        int l = len_of_cell(p, ec[x]);
-        c.push_back({pv, l, (int64_t)ec[x] - p.len[l].cell_base});
+        const int l = len_of_cell(p, ec[x]);
+        c.push_back({pv, l, (int64_t)ec[x] - p.len[l].cell_base, ek[x]});
     }
     // greedy (Sec. 2): skip a cell within m/2 of an accepted cell of its length
     for (const Cand &x : c) {
@@ -561,12 +570,12 @@ static size_t upper_bytes(int64_t n, int m_min, int m_max, const Opt &o, int k) 
     plan_lengths(p, n, m_min, m_max, o.m_step);
     std::vector<int64_t> cnt(p.L);
     for (int l = 0; l < p.L; ++l) cnt[l] = p.len[l].W;
-    plan_index(p, cnt, o, 1);     // alpha = 1 gives the deepest directories
+    plan_index(p, cnt, o, 1, kMaxK);   // alpha = 1 gives the deepest directories
     Arena a;
     a.sizing = true;
     Bufs b;
     carve1(a, b, p, k);
-    carve2(a, b, p, o.precision);
+    carve2(a, b, p, o.precision, k);
     return a.off + 4096;
 }
 
@@ -582,19 +591,33 @@ struct Run {
     pmp_debug *dbg;
 };
 
-__global__ void k_debug_sigma(const double *__restrict__ isig, int64_t n, double *__restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) out[i] = isig[i] != 0.0 ? 1.0 / isig[i] : 0.0;
+// debug exports: per-k arrays to per-cell arrays (constant cells keep the fill)
+__global__ void k_debug_scatter(const uint32_t *__restrict__ cell, int64_t N,
+                                const uint64_t *__restrict__ src, int invert,
+                                uint64_t *__restrict__ dst) {
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= N) return;
+    uint64_t v = src[k];
+    if (invert) {       // 1/isig -> sigma
+        double x = __longlong_as_double((long long)v);
+        v = (uint64_t)__double_as_longlong(1.0 / x);
+    }
+    dst[cell[k]] = v;
 }
 
 template <typename FT>
-__global__ void k_debug_features(const FT *__restrict__ F, const uint32_t *__restrict__ inv,
-                                 const double *__restrict__ isig, int64_t cells,
-                                 FT *__restrict__ out) {
-    int64_t c = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
+__global__ void k_debug_features(const FT *__restrict__ F, const uint32_t *__restrict__ cell,
+                                 int64_t N, FT *__restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * 8 + threadIdx.x / 32;
     int e = threadIdx.x % 32;
-    if (c >= cells) return;
-    out[c * kRec + e] = isig[c] != 0.0 ? F[(int64_t)inv[c] * kRec + e] : (FT)0;
+    if (k >= N) return;
+    out[(int64_t)cell[k] * kRec + e] = F[k * kRec + e];
+}
+
+__global__ void k_debug_perm(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ cell,
+                             int64_t N, uint32_t *__restrict__ out) {
+    int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s < N) out[s] = cell[perm[s]];
 }
 
 static int run_pipeline(Run &R, Arena &ar) {
@@ -609,23 +632,24 @@ static int run_pipeline(Run &R, Arena &ar) {
     Timer tm;
     tm.mark(0, s);
 
-    // ---- validation, change points, index counts
+    // ---- validation, change points, index counts per tile
     HIPCHK(hipMemsetAsync(b.bad, 0, sizeof(int), s));
     launch_changepoints(R.t, R.n, b.flags, b.bad, s);
     scan_exclusive_u32(b.flags, b.E, R.n + 1, nullptr, b.scan_tmp, s);
     HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(b.counts, 0, p.L * sizeof(unsigned long long), s));
-    launch_count_index(b.len, p.L, b.E, b.counts, p.len[0].W, s);
+    launch_tile_counts(b.len, p.L, b.E, p.ntiles, b.tile_off, s);
+    HIPCHK(hipMemsetAsync(b.tile_off + p.ntiles, 0, sizeof(uint32_t), s));
+    scan_exclusive_u32(b.tile_off, b.tile_off, p.ntiles + 1, nullptr, b.scan_tmp, s);
     int bad = 0;
-    std::vector<int64_t> cnt(p.L);
+    std::vector<uint32_t> toff(p.ntiles + 1);
     HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(cnt.data(), b.counts, p.L * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(toff.data(), b.tile_off, (p.ntiles + 1) * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, s));
     // calibration samples
     std::vector<int> cal_m;
     std::vector<std::vector<int64_t>> cal_st;
     if (o.K == 0) {
         int idx[3] = {0, (p.L - 1) / 2, p.L - 1};
-        std::vector<int64_t> all;
         for (int a = 0; a < 3; ++a) {
             if (a > 0 && idx[a] == idx[a - 1]) continue;
             cal_m.push_back(p.ms[idx[a]]);
@@ -655,11 +679,16 @@ static int run_pipeline(Run &R, Arena &ar) {
             }
         K = calibrate(sets, cal_m, R.n, R.budget, o.gamma, o.B);
     }
-    plan_index(p, cnt, o, R.budget);
-    for (int l = 0; l < p.L; ++l) p.len[l].kprime = kprime_of(K, p.ms[l]);
-    if (p.N >= (int64_t)UINT32_MAX - 1) return fail(PMP_EINVAL, "too many windows");
-    carve2(ar, b, p, o.precision);
+    std::vector<int64_t> cnt(p.L);
+    for (int l = 0; l < p.L; ++l) {
+        const int64_t t1 = l + 1 < p.L ? p.len[l + 1].tile_base : p.ntiles;
+        cnt[l] = (int64_t)toff[t1] - (int64_t)toff[p.len[l].tile_base];
+    }
+    plan_index(p, cnt, o, R.budget, K);
+    if (p.N != (int64_t)toff[p.ntiles]) return fail(PMP_EINTERNAL, "index count mismatch");
+    carve2(ar, b, p, o.precision, R.k);
     if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
+    const int64_t N = p.N;
 
     // ---- per-request constants
     {
@@ -678,10 +707,8 @@ static int run_pipeline(Run &R, Arena &ar) {
         HIPCHK(hipMemcpyAsync(b.prange, pr.data(), p.L * sizeof(float), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
     }
-    launch_fill_u64(b.P, p.cells, kInfBits, s);
     HIPCHK(hipMemsetAsync(b.emax, 0, p.L * sizeof(float), s));
     HIPCHK(hipMemsetAsync(b.counters, 0, C_NCOUNTERS * sizeof(unsigned long long), s));
-    HIPCHK(hipMemsetAsync(b.bstart, 0, (p.nbuckets + 1) * sizeof(uint32_t), s));
 
     Req q{};
     q.t = R.t;
@@ -695,38 +722,34 @@ static int run_pipeline(Run &R, Arena &ar) {
     q.jkey_shift = p.jkey_shift;
     q.precision = o.precision;
     q.len = b.len;
-    q.cpre = (const int32_t *)b.E;
+    q.cell = b.cell;
     q.mu = b.mu;
     q.isig = b.isig;
     q.P = b.P;
-    q.keyw_nat = b.keyw_nat;
-    q.skey = b.skey;
-    q.sval = b.sval;
-    q.bucket_cnt = b.bstart;
-    q.perm = b.sval;
-    q.inv = b.inv;
     q.F = b.F;
     q.keyw = b.keyw;
+    q.jrec = b.jrec;
+    q.skey = b.skey;
+    q.sval = b.sval;
+    q.perm = b.sval;
+    q.pcell = b.pcell;
+    q.inv = b.inv;
     q.gproj = b.gproj;
     q.ujoin = b.ujoin;
-    q.jrec = b.jrec;
     q.emax = b.emax;
     q.counters = b.counters;
     q.bad = b.bad;
 
-    // ---- pass A, buckets, pass B
+    // ---- one sketch pass, buckets
     tm.mark(1, s);
-    launch_sketch(0, o.precision, q, b.E, b.tile_cnt, p.ntiles, p.max_m, s);
-    scan_exclusive_u32(b.tile_cnt, b.tile_cnt, p.ntiles, nullptr, b.scan_tmp, s);
-    launch_emit_sortin(q, b.tile_cnt, p.ntiles, s);
+    launch_sketch(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, s);
     tm.mark(2, s);
-    radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, p.N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
-    scan_exclusive_u32(b.bstart, b.bstart, p.nbuckets + 1, nullptr, b.scan_tmp, s);
-    launch_invert(b.sval, p.N, b.inv, s);
+    radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
+    launch_bucket_bounds(q, N, p.nbuckets, b.bstart, s);
+    launch_slot_maps(q, N, s);
     tm.mark(3, s);
-    launch_sketch(1, o.precision, q, b.E, b.tile_cnt, p.ntiles, p.max_m, s);
     tm.mark(4, s);
-    launch_probe(o.precision, q, b.bstart, p.N, s);
+    launch_probe(o.precision, q, b.bstart, N, s);
     launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
     tm.mark(5, s);
     HIPCHK(hipGetLastError());
@@ -734,19 +757,24 @@ static int run_pipeline(Run &R, Arena &ar) {
     HIPCHK(hipStreamSynchronize(s));
     if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
 
-    if (R.dbg && R.dbg->profile_pass)
-        HIPCHK(hipMemcpyAsync(R.dbg->profile_pass, b.P, p.cells * 8, hipMemcpyDeviceToDevice, s));
+    if (R.dbg && R.dbg->profile_pass) {
+        launch_fill_u64((uint64_t *)R.dbg->profile_pass, p.cells, kInfBits, s);
+        if (N)
+            hipLaunchKernelGGL(k_debug_scatter, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                               b.cell, N, b.P, 0, (uint64_t *)R.dbg->profile_pass);
+    }
 
     // ---- selection on the upper profile
     std::vector<Cand> acc;
-    int rc = select_topk(p, b, b.P, R.k, s, acc);
+    int rc = select_topk(p, b, R.k, s, acc);
     if (rc) return rc;
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
-    if (o.certify) {
-        launch_join_keys(q, b.prange, p.N, b.jk, b.jv, s);
-        radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, p.N, 0, p.jkey_shift + p.len_bits, b.sort_tmp, s);
-        launch_join_gather(b.jrec, b.jv, p.N, b.jsorted, s);
+    if (o.certify && N > 0) {
+        launch_join_keys(q, b.prange, N, b.jk, b.jv, s);
+        radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.jkey_shift + p.len_bits, b.sort_tmp, s);
+        launch_join_gather(b.jrec, b.jv, N, b.jsorted, s);
+        launch_invert(b.jv, N, b.jinv, s);
         std::vector<float> emax(p.L);
         HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -771,9 +799,14 @@ static int run_pipeline(Run &R, Arena &ar) {
                 jl[l].pad = 0.0f;
             }
             HIPCHK(hipMemcpyAsync(b.jl, jl.data(), p.L * sizeof(JoinLen), hipMemcpyHostToDevice, s));
-            launch_join(o.precision, q, b.jsorted, b.jk, b.jl, p.N, Teff, s);
+            HIPCHK(hipMemsetAsync(b.jq_count, 0, sizeof(uint32_t), s));
+            launch_join_queries(q, b.jinv, N, b.jq, b.jq_count, s);
+            uint32_t nq = 0;
+            HIPCHK(hipMemcpyAsync(&nq, b.jq_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            launch_join(o.precision, q, b.jsorted, b.jk, b.jl, b.jq, nq, N, Teff, s);
             HIPCHK(hipGetLastError());
-            rc = select_topk(p, b, b.P, R.k, s, acc);
+            rc = select_topk(p, b, R.k, s, acc);
             if (rc) return rc;
             if (std::isinf(T)) break;                               // exhaustive
             if (acc.size() == (size_t)R.k && acc.back().d <= T) break;
@@ -786,10 +819,12 @@ static int run_pipeline(Run &R, Arena &ar) {
     // ---- exact rows of the reported cells
     const int nacc = (int)acc.size();
     std::vector<RowReq> rr(nacc);
+    int64_t maxN = 1;
+    for (int l = 0; l < p.L; ++l) maxN = std::max(maxN, p.len[l].n_index);
     for (int x = 0; x < nacc; ++x) {
         rr[x].l = acc[x].l;
         rr[x].pad = 0;
-        rr[x].i = acc[x].i;
+        rr[x].k = acc[x].k;
         double d = acc[x].d;
         memcpy(&rr[x].target, &d, 8);
     }
@@ -799,7 +834,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         launch_fill_u64((uint64_t *)b.row_min, nacc, kInfBits, s);
         launch_fill_u64((uint64_t *)b.row_arg, nacc, ~0ull, s);
         if (o.certify) {
-            launch_rows(q, b.rows, nacc, p.len[0].W, 1, b.row_min, b.row_arg, s);
+            launch_rows(q, b.rows, nacc, maxN, 1, b.row_min, b.row_arg, s);
             HIPCHK(hipMemcpyAsync(rmin.data(), b.row_min, nacc * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             for (int x = 0; x < nacc; ++x)
@@ -813,7 +848,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                                 p.ms[acc[x].l], (long long)acc[x].i, a, bq);
                 }
         }
-        launch_rows(q, b.rows, nacc, p.len[0].W, 0, b.row_min, b.row_arg, s);
+        launch_rows(q, b.rows, nacc, maxN, 0, b.row_min, b.row_arg, s);
         HIPCHK(hipMemcpyAsync(rarg.data(), b.row_arg, nacc * 8, hipMemcpyDeviceToHost, s));
     }
     tm.mark(7, s);
@@ -836,26 +871,42 @@ static int run_pipeline(Run &R, Arena &ar) {
             if (d->depth) d->depth[l] = p.len[l].depth;
             if (d->indexed) d->indexed[l] = p.len[l].n_index;
         }
-        if (d->mu) HIPCHK(hipMemcpyAsync(d->mu, b.mu, p.cells * 8, hipMemcpyDeviceToDevice, s));
-        if (d->sigma)
-            hipLaunchKernelGGL(k_debug_sigma, dim3((unsigned)((p.cells + 255) / 256)), dim3(256), 0, s,
-                               b.isig, p.cells, d->sigma);
-        if (d->profile_final)
-            HIPCHK(hipMemcpyAsync(d->profile_final, b.P, p.cells * 8, hipMemcpyDeviceToDevice, s));
-        if (d->keys) HIPCHK(hipMemcpyAsync(d->keys, b.keyw_nat, p.cells * 8, hipMemcpyDeviceToDevice, s));
-        if (d->perm) HIPCHK(hipMemcpyAsync(d->perm, b.sval, p.N * 4, hipMemcpyDeviceToDevice, s));
+        const unsigned gb = (unsigned)((std::max<int64_t>(N, 1) + 255) / 256);
+        if (d->mu) {
+            HIPCHK(hipMemsetAsync(d->mu, 0, p.cells * 8, s));
+            if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N,
+                                      (const uint64_t *)b.mu, 0, (uint64_t *)d->mu);
+        }
+        if (d->sigma) {
+            HIPCHK(hipMemsetAsync(d->sigma, 0, p.cells * 8, s));
+            if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N,
+                                      (const uint64_t *)b.isig, 1, (uint64_t *)d->sigma);
+        }
+        if (d->profile_final) {
+            launch_fill_u64((uint64_t *)d->profile_final, p.cells, kInfBits, s);
+            if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N, b.P, 0,
+                                      (uint64_t *)d->profile_final);
+        }
+        if (d->keys) {
+            launch_fill_u64(d->keys, p.cells, ~0ull, s);
+            if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N, b.keyw,
+                                      0, d->keys);
+        }
+        if (d->perm && N)
+            hipLaunchKernelGGL(k_debug_perm, dim3(gb), dim3(256), 0, s, b.sval, b.cell, N, d->perm);
         if (d->bucket_start)
             HIPCHK(hipMemcpyAsync(d->bucket_start, b.bstart, (p.nbuckets + 1) * 4,
                                   hipMemcpyDeviceToDevice, s));
         if (d->features) {
-            if (o.precision == 0)
-                hipLaunchKernelGGL(k_debug_features<double>, dim3((unsigned)((p.cells + 7) / 8)),
-                                   dim3(256), 0, s, (const double *)b.F, b.inv, b.isig, p.cells,
-                                   (double *)d->features);
-            else
-                hipLaunchKernelGGL(k_debug_features<float>, dim3((unsigned)((p.cells + 7) / 8)),
-                                   dim3(256), 0, s, (const float *)b.F, b.inv, b.isig, p.cells,
-                                   (float *)d->features);
+            const size_t fb = (size_t)p.cells * kRec * (o.precision == 0 ? 8 : 4);
+            HIPCHK(hipMemsetAsync(d->features, 0, fb, s));
+            const unsigned fbk = (unsigned)((std::max<int64_t>(N, 1) + 7) / 8);
+            if (N && o.precision == 0)
+                hipLaunchKernelGGL(k_debug_features<double>, dim3(fbk), dim3(256), 0, s,
+                                   (const double *)b.F, b.cell, N, (double *)d->features);
+            else if (N)
+                hipLaunchKernelGGL(k_debug_features<float>, dim3(fbk), dim3(256), 0, s,
+                                   (const float *)b.F, b.cell, N, (float *)d->features);
         }
         HIPCHK(hipStreamSynchronize(s));
     }
@@ -868,7 +919,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->lengths = p.L;
         st->certify_rounds = rounds;
         st->cells = (uint64_t)p.cells;
-        st->indexed_cells = (uint64_t)p.N;
+        st->indexed_cells = (uint64_t)N;
         st->pass_candidates = ctr[C_PASS_CAND];
         st->pass_verified = ctr[C_PASS_VER];
         st->join_candidates = ctr[C_JOIN_CAND];
@@ -879,7 +930,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->ms_total = tm.ms(0, 7);
         st->ms_onepass = tm.ms(0, 5);
         st->ms_certify = tm.ms(5, 7);
-        st->ms_sketch = tm.ms(1, 2) + tm.ms(3, 4);
+        st->ms_sketch = tm.ms(1, 2);
         st->ms_sort = tm.ms(2, 3);
         st->ms_probe = tm.ms(4, 5);
         st->ms_join = tm.ms(5, 6);

@@ -157,9 +157,11 @@ def test_moments_features_keys(gpu, ws, oracle, prec):
     for li, m in enumerate(lengths):
         W = len(t) - m + 1
         omu, osig, ocst = oracle.window_stats(t, m)
-        # a1: moments (two-pass, same formula) and constant flags
-        np.testing.assert_array_equal(mu[base:base + W][~ocst], omu[~ocst])
-        np.testing.assert_allclose(sig[base:base + W][~ocst], osig[~ocst], rtol=2e-16 * 4)
+        # a1: moments (two-pass; the kernel sums in four interleaved partial
+        # sums, so agreement is to rounding, relative to the window scale)
+        scale = np.max(np.abs(t))
+        np.testing.assert_allclose(mu[base:base + W][~ocst], omu[~ocst], rtol=0, atol=1e-13 * scale)
+        np.testing.assert_allclose(sig[base:base + W][~ocst], osig[~ocst], rtol=1e-12)
         assert np.array_equal(sig[base:base + W] == 0.0, ocst)
         assert host["indexed"][li] == int((~ocst).sum())
         # a2: features within the bound the library derives for them
