@@ -89,6 +89,8 @@ struct SketchSmem {
     int32_t kpos[kTileW];                 // indexed position, -1 for constant windows
     float ymax[kSegs];
     float mg[kRows][kMaxBits + 1];        // |<g_l, F>| of each row
+    uint32_t sigp[kRows][4];              // signature bits, one part per quad thread
+    int32_t seg_any[kSegs];               // segment holds an indexed window
     float g[kMaxBits][kFD];
     uint32_t wsum[kBlock / kWave];
     int emax;
@@ -188,6 +190,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
             run += tot;
             __syncthreads();
         }
+        if (tid < kSegs) {
+            int any = 0;
+            for (int w = tid * kSegW; w < min(nw, (tid + 1) * kSegW); ++w) any |= sm.kpos[w] >= 0;
+            sm.seg_any[tid] = any;
+        }
+        __syncthreads();
     }
 
     // ---- sliding DFT in FP64: thread (segment g, bin b)
@@ -205,7 +213,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         if (b == 0) sm.ymax[g] = (float)(Y * (1.0 + 1e-6)) * (1.0f + 1e-6f);
     }
     double xr = 0.0, xi = 0.0, wcos = 1.0, wsin = 0.0;
-    const bool own = segn > 0 && b < kp;
+    // a segment of constant windows only has no feature to compute
+    const bool own = segn > 0 && b < kp && sm.seg_any[g];
     if (own) {
         const int k = b + 1;
         sincospi(2.0 * (double)k / (double)m, &wsin, &wcos);   // omega = e^{+2 pi i k/m}
@@ -278,47 +287,47 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         const bool valid = s < nw;
         const int32_t kk = valid ? sm.kpos[s] : -1;
         const bool indexed = kk >= 0;
+        // constant windows (no cell) skip the arithmetic below
         float f[kFD];
-#pragma unroll
-        for (int x = 0; x < kFD; ++x) f[x] = (float)stage[row][x];
-        // SimHash bits (Sec. 3.4): bit l = [<g_l, F> >= 0], six per thread;
-        // margins go to LDS so that no register array is indexed at run time
-        uint32_t sig = 0;
-#pragma unroll
-        for (int h = 0; h < 6; ++h) {
-            const int bt = quad * 6 + h;
-            if (bt < q.B) {
-                float dot = 0.0f;
-#pragma unroll
-                for (int x = 0; x < kFD; ++x) dot = fmaf(sm.g[bt][x], f[x], dot);
-                sm.mg[row][bt] = fabsf(dot);
-                if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
-            }
-        }
-        sig |= __shfl_xor(sig, 1, kWave);
-        sig |= __shfl_xor(sig, 2, kWave);
-        // join record: orthonormal projections of the FP32 copy, FP64 dots
-        float *jr = q.jrec + (int64_t)(indexed ? kk : 0) * 8;
-#pragma unroll
-        for (int dd = 0; dd < 2; ++dd) {
-            const int dim = quad + 4 * dd;
-            if (dim < kJoinDims && indexed) {
-                double p = 0.0;
-#pragma unroll
-                for (int x = 0; x < kFD; ++x) p = fma(q.ujoin[dim * kFD + x], (double)f[x], p);
-                jr[dim] = (float)p;
-            }
-        }
-        // norm of the FP32 copy, across the quad
         double n2 = 0.0;
+        if (indexed) {
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const int xx = quad * 8 + x;
-            if (xx < kFD) n2 += (double)f[xx] * (double)f[xx];
+            for (int x = 0; x < kFD; ++x) f[x] = (float)stage[row][x];
+            // SimHash bits (Sec. 3.4): bit l = [<g_l, F> >= 0], six per
+            // thread; margins and bits go to LDS, so no register array is
+            // indexed at run time and no cross-lane exchange is needed
+            uint32_t sig = 0;
+#pragma unroll
+            for (int h = 0; h < 6; ++h) {
+                const int bt = quad * 6 + h;
+                if (bt < q.B) {
+                    float dot = 0.0f;
+#pragma unroll
+                    for (int x = 0; x < kFD; ++x) dot = fmaf(sm.g[bt][x], f[x], dot);
+                    sm.mg[row][bt] = fabsf(dot);
+                    if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
+                }
+            }
+            sm.sigp[row][quad] = sig;
+            // join record: orthonormal projections of the FP32 copy, FP64 dots
+            float *jr = q.jrec + (int64_t)kk * 8;
+#pragma unroll
+            for (int dd = 0; dd < 2; ++dd) {
+                const int dim = quad + 4 * dd;
+                if (dim < kJoinDims) {
+                    double p = 0.0;
+#pragma unroll
+                    for (int x = 0; x < kFD; ++x) p = fma(q.ujoin[dim * kFD + x], (double)f[x], p);
+                    jr[dim] = (float)p;
+                }
+            }
+            // norm of the FP32 copy (static register indices only)
+            if (quad == 0) {
+#pragma unroll
+                for (int x = 0; x < kFD; ++x) n2 = fma((double)f[x], (double)f[x], n2);
+            }
         }
-        n2 += __shfl_xor(n2, 1, kWave);
-        n2 += __shfl_xor(n2, 2, kWave);
-        __syncthreads();                      // margins visible to the quad leader
+        __syncthreads();                      // margins and bits visible to the quad leader
         if (indexed && quad == 0) {
             // Hamming-1 probe order: the `probes` smallest margins among the
             // d prefix bits, ascending (Sec. 3.4 multi-probe)
@@ -335,10 +344,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
                 used |= 1u << best;
                 order |= (uint64_t)best << (5 * h);
             }
+            const uint32_t sig = sm.sigp[row][0] | sm.sigp[row][1] | sm.sigp[row][2] | sm.sigp[row][3];
             q.keyw[kk] = (uint64_t)sig | (order << 24);
             const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
             q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
             q.sval[kk] = (uint32_t)kk;
+            float *jr = q.jrec + (int64_t)kk * 8;
             jr[6] = __uint_as_float((uint32_t)kk);
             jr[7] = 0.0f;
             // error bound of the stored features (see file comment): direct
