@@ -74,6 +74,78 @@ def cpu_baseline(t, name, target_s=12.0):
                       f"{el:.1f} s"}
 
 
+TILE_W = 1024          # windows per sketch tile
+REC = 32               # feature record slots per window (30 features, error, norm)
+
+
+def algorithmic_bytes(n, lengths, st, fs):
+    """Bytes each main kernel must move per launch (the model stated in the
+    design notes): fs is the size of a stored feature (8 FP64, 4 FP32)."""
+    rd = 0
+    for m in lengths:
+        w = n - m + 1
+        rd += 12 * (w + -(-w // TILE_W) * (m - 1))   # samples + change-point prefix
+    nx = st["indexed_cells"]
+    # per indexed window: cell, mu, 1/sigma, P, record, key word, sort key and
+    # value, join record
+    sketch = rd + nx * (4 + 8 + 8 + 8 + REC * fs + 8 + 4 + 4 + 32)
+    # per query: its state; per inspected candidate: slot, P, record; per
+    # verified pair: the candidate's moments and the two cell updates (the
+    # samples of both windows are read from the series, which stays resident
+    # in the caches: 8 n bytes in all)
+    probe = (nx * (REC * fs + 4 + 4 + 8 + 8 + 8 + 8 + 4)
+             + st["pass_candidates"] * (REC * fs + 4 + 4 + 8)
+             + st["pass_verified"] * (16 + 16) + 8 * n)
+    join = (nx * 32 + st["join_candidates"] * (REC * fs + 4)
+            + st["join_verified"] * (16 + 16) + 8 * n)
+    return {"k_sketch": float(sketch), "k_probe": float(probe), "k_join": float(join)}
+
+
+KERNEL_SOURCES = {"k_sketch": "k_sketch.hip", "k_probe": "k_probe.hip", "k_join": "k_certify.hip"}
+
+
+def source_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCES[kernel], "pmp_dev.h"):
+        with open(os.path.join(ROOT, "paper_2607_17481_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none for this kernel/workload or the kernel's source changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    want = source_digest(kernel)
+    for line in open(path):
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        if (len(cols) >= 6 and cols[0] == kernel and cols[1] == workload
+                and cols[2] == precision and cols[-1] == want):
+            try:
+                return float(cols[5])
+            except ValueError:
+                return None
+    return None
+
+
+def copy_calibration():
+    """A plain copy kernel of known size (1 GiB read, 1 GiB written), run
+    under the same counters as the kernels to scale FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel": "neg", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,11 +154,16 @@ def main():
     ap.add_argument("--workload", default="wafer5m", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the copy kernel that scales the HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the workload fits one MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_2607_17481_amd import pmp
@@ -115,16 +192,16 @@ def main():
     value = cells * args.steps / el
     avg = lambda key: float(np.mean([s[key] for s in stats]))  # noqa: E731
 
-    # dominant kernel: the probe / prune / verify pass; algorithmic bytes per
-    # launch from the work it did (see the design notes for the model)
-    rec = 256 if args.precision == "fp64" else 128
+    # dominant kernel: the largest of the three main kernels by the library's
+    # own HIP-event brackets (recorded on the stream the kernels run on)
     last = stats[-1]
-    m_bar = float(np.mean(range(m_min, m_max + 1, step)))
-    alg_bytes = (last["indexed_cells"] * (rec + 8 + 16)
-                 + last["pass_candidates"] * (rec + 4 + 8)
-                 + last["pass_verified"] * (2 * 8 * m_bar + 16))
-    probe_ms = avg("ms_probe")
-    achieved = alg_bytes / (probe_ms * 1e-3) / 1e9
+    lengths = list(range(m_min, m_max + 1, step))
+    fs = 8 if args.precision == "fp64" else 4
+    alg = algorithmic_bytes(n, lengths, last, fs)
+    kern_ms = {"k_sketch": avg("ms_sketch"), "k_probe": avg("ms_probe"), "k_join": avg("ms_join")}
+    dom = max(kern_ms, key=kern_ms.get)
+    achieved = alg[dom] / (kern_ms[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, args.workload, args.precision)
     line = {
         "metric": "samples*lengths/sec to exact top-20 pan-motifs",
         "value": value,
@@ -146,9 +223,16 @@ def main():
         "phase_ms": {p: avg("ms_" + p) for p in ("sketch", "sort", "probe", "join", "rows")},
         "certify_rounds": last["certify_rounds"],
         "K": last["K"],
-        "roofline": {"kernel": "k_probe", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": traffic, "algorithmic_bytes": alg[dom],
+                     "kernel_ms": kern_ms[dom]},
+        "kernel_ms": kern_ms,
+        "indexed_cells": last["indexed_cells"],
+        "pass_candidates": last["pass_candidates"],
+        "pass_verified": last["pass_verified"],
+        "join_candidates": last["join_candidates"],
+        "join_verified": last["join_verified"],
         "top1": [res[0].i, res[0].j, res[0].m, res[0].dist] if res else None,
     }
     if not args.no_cpu_baseline:
