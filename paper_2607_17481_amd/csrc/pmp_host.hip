@@ -2,9 +2,8 @@
 //
 // One request runs, on one HIP stream:
 //   change points -> per-length index counts -> depths            (host sync)
-//   pass A: moments + features + SimHash keys      (k_sketch<0>)
-//   ordered compaction + stable radix sort into buckets
-//   pass B: features in bucket order + join records (k_sketch<1>)
+//   one sketch pass: moments, features, SimHash keys, join records (k_sketch)
+//   stable radix sort into buckets, bucket starts, slot maps
 //   probe / Parseval prune / exact verification     (k_probe)      -> upper profile
 //   top-k selection (radix select + greedy)                        (host sync)
 //   certificate: threshold join at T, repeated while needed         (k_join)
