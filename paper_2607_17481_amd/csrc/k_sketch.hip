@@ -81,32 +81,174 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const LenInfo *__restric
 
 namespace {
 
-constexpr int kFD = 2 * (kMaxK - 1);      // 30 feature reals
-constexpr int kRows = kSegs * kChunk;     // windows per post-processing step (64)
+constexpr int kFD = 2 * (kMaxK - 1);          // 30 feature reals
+constexpr int kRowsC = 128;                   // staged windows per chunk
+constexpr int kSlidesC = kRowsC / kSegs;      // slides per segment per chunk (8)
+constexpr int kStageLd = 31;                  // doubles per staged row (odd: the
+                                              // row threads' 8-byte reads spread
+                                              // over all banks)
 
 struct SketchSmem {
-    double isig[kTileW];
-    int32_t kpos[kTileW];                 // indexed position, -1 for constant windows
-    float ymax[kSegs];
-    float mg[kRows][kMaxBits + 1];        // |<g_l, F>| of each row
-    uint32_t sigp[kRows][4];              // signature bits, one part per quad thread
-    int32_t seg_any[kSegs];               // segment holds an indexed window
-    float g[kMaxBits][kFD];
+    int32_t kpos[kTileW];                     // indexed position, -1: constant window
+    float ymax[kSegs];                        // largest |t - c| of each segment
     uint32_t wsum[kBlock / kWave];
     int emax;
 };
 
+// Post-processing of one indexed window (one thread): two-pass moments, the
+// normalized features F = X / sigma written to the record, SimHash bits and
+// the Hamming-1 probe order (Sec. 3.4), the join projections, and the
+// error bound e_i of the stored features.
+template <typename FT>
+__device__ __forceinline__ void sketch_row(const Req &q, const LenInfo &L, int l, int64_t cell,
+                                           const double *__restrict__ x, int rot,
+                                           const double *__restrict__ X, float Ymax, int kk,
+                                           const float *__restrict__ gl,
+                                           const double *__restrict__ uj, float &emax) {
+    const int m = L.m;
+    // ---- moments, two passes (Sec. 3.2); each sum starts at sample `rot`
+    // and wraps around, so that the row groups of a wavefront, whose windows
+    // lie 64 apart, read different LDS banks
+    double a0 = 0.0, a1 = 0.0;
+    {
+        int r = rot;
+        for (int j = 0; j < m; ++j) {
+            if (j & 1) a1 += x[r]; else a0 += x[r];
+            r = r + 1 == m ? 0 : r + 1;
+        }
+    }
+    const double mu = (a0 + a1) / (double)m;
+    a0 = 0.0;
+    a1 = 0.0;
+    {
+        int r = rot;
+        for (int j = 0; j < m; ++j) {
+            const double c = x[r] - mu;
+            if (j & 1) a1 = fma(c, c, a1); else a0 = fma(c, c, a0);
+            r = r + 1 == m ? 0 : r + 1;
+        }
+    }
+    const double sg = sqrt((a0 + a1) / (double)m);
+    double is = 1.0 / sg;
+    if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
+        // samples differ but sigma underflows or overflows: outside the
+        // range the library represents; the window stays indexed so every
+        // count stays consistent, and the call fails
+        atomicOr(q.bad, 2);
+        is = 1.0;
+    }
+    q.cell[kk] = (uint32_t)cell;
+    q.mu[kk] = mu;
+    q.isig[kk] = is;
+    q.P[kk] = kInfBits;
+
+    // ---- features: scale, store, keep an FP32 copy
+    FT *rec = (FT *)q.F + (int64_t)kk * kRec;
+    float f[kFD];
+    double n2 = 0.0;
+#pragma unroll
+    for (int p = 0; p < kFD / 2; ++p) {
+        const double vr = X[2 * p] * is, vi = X[2 * p + 1] * is;
+        f[2 * p] = (float)vr;
+        f[2 * p + 1] = (float)vi;
+        if (sizeof(FT) == 8) {
+            double2 v;
+            v.x = vr;
+            v.y = vi;
+            *(double2 *)(rec + 2 * p) = v;
+        }
+    }
+    if (sizeof(FT) == 4) {
+#pragma unroll
+        for (int p = 0; p < 7; ++p)
+            *(float4 *)(rec + 4 * p) = make_float4(f[4 * p], f[4 * p + 1], f[4 * p + 2], f[4 * p + 3]);
+    }
+#pragma unroll
+    for (int x2 = 0; x2 < kFD; ++x2) n2 = fma((double)f[x2], (double)f[x2], n2);
+
+    // ---- SimHash bits: bit b = [<g_b, F> >= 0], most significant first
+    uint32_t sig = 0;
+    uint32_t key[kMaxBits];
+#pragma unroll
+    for (int bt = 0; bt < kMaxBits; ++bt) {
+        key[bt] = 0xFFFFFFFFu;
+        if (bt < q.B) {
+            float dot = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kFD; ++c) dot = fmaf(gl[bt * kFD + c], f[c], dot);
+            if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
+            // probe key: the margin |dot| (its order is the order of the
+            // bit patterns) with the bit index in the low five bits
+            if (bt < L.depth) key[bt] = (__float_as_uint(fabsf(dot)) & ~31u) | (uint32_t)bt;
+        }
+    }
+    // ---- Hamming-1 probe order: the `probes` smallest margins among the
+    // d prefix bits, ascending (Sec. 3.4 multi-probe)
+    uint64_t order = 0;
+    for (int h = 0; h < L.probes; ++h) {
+        uint32_t mn = key[0];
+#pragma unroll
+        for (int bt = 1; bt < kMaxBits; ++bt) mn = min(mn, key[bt]);
+        order |= (uint64_t)(mn & 31u) << (5 * h);
+#pragma unroll
+        for (int bt = 0; bt < kMaxBits; ++bt) key[bt] = key[bt] == mn ? 0xFFFFFFFFu : key[bt];
+    }
+    q.keyw[kk] = (uint64_t)sig | (order << 24);
+    const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
+    q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
+    q.sval[kk] = (uint32_t)kk;
+
+    // ---- join record: orthonormal projections of the FP32 copy, FP64 dots
+    float jp[kJoinDims];
+#pragma unroll
+    for (int dm = 0; dm < kJoinDims; ++dm) {
+        double p = 0.0;
+#pragma unroll
+        for (int c = 0; c < kFD; ++c) p = fma(uj[dm * kFD + c], (double)f[c], p);
+        jp[dm] = (float)p;
+    }
+    float4 *jr = (float4 *)(q.jrec + (int64_t)kk * 8);
+    jr[0] = make_float4(jp[0], jp[1], jp[2], jp[3]);
+    jr[1] = make_float4(jp[4], jp[5], __uint_as_float((uint32_t)kk), 0.0f);
+
+    // ---- error bound of the stored features: the direct start (four
+    // quarters) and up to 63 slides in FP64, the scaling by 1/sigma, and the
+    // rounding to FT; the FP32 copy is within u32 |F| of the FP64 value, which
+    // also bounds the norm used here
+    const double nrm = sqrt(n2) * (1.0 + 1e-6) + 1e-30;
+    const double u64 = 1.1102230246251565e-16;
+    const double ust = sizeof(FT) == 4 ? 5.9604644775390625e-08 : u64;
+    const double Ebin = (6.0 * m * (double)m + 8.0 * kSegW * (m + 2.0) + 2.0 * m) * u64 * (double)Ymax;
+    const double ecomp = sqrt(2.0 * L.kprime) * Ebin * is * 1.001;
+    const double estore = (ust + 4.0 * u64) * (nrm + 6e-8 * nrm) * 1.001;
+    const float e = (float)((ecomp + estore) * (1.0 + 1e-6)) * (1.0f + 2.4e-7f) + 1e-30f;
+    if (sizeof(FT) == 8) {
+        double2 v;
+        v.x = (double)e;
+        v.y = nrm;
+        *(double2 *)(rec + kSlotErr) = v;
+    } else {
+        *(float4 *)(rec + 28) = make_float4(f[28], f[29], e, (float)nrm);
+    }
+    emax = fmaxf(emax, e);
+}
+
 }  // namespace
 
-// One block per tile of 1024 consecutive windows of one length.  Thread
-// (segment g = tid / 16, bin b = tid % 16) owns bin k = b + 1 of the 64
-// windows of segment g: it computes the bin directly at the segment start
-// (four independent phasor chains, so the sum is not one long dependent
-// chain) and slides it 63 times.  Every 4 slides the 64 new windows are
-// post-processed by four threads each.
+// One block per tile of 1024 consecutive windows of one length.
+//  1. samples into LDS; compacted position of every non-constant window;
+//  2. thread (segment g = tid / 16, bin b = tid % 16) owns bin k = b + 1 of
+//     the 64 windows of segment g: it computes the bin directly at the
+//     segment start (four independent phasor chains, so the sum is not one
+//     long dependent chain) and slides it 63 times, in FP64;
+//  3. every 8 slides the 128 new windows' raw bins are staged in LDS and one
+//     thread per window finishes it (sketch_row).
 template <typename FT>
 __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__restrict__ E,
-                                                      const uint32_t *__restrict__ tile_off) {
+                                                      const uint32_t *__restrict__ tile_off,
+                                                      int st_len,
+                                                      const float *__restrict__ gproj,
+                                                      const double *__restrict__ ujoin) {
     extern __shared__ double dyn[];
     __shared__ SketchSmem sm;
     const int64_t tile = blockIdx.x;
@@ -119,84 +261,39 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wv = tid / kWave;
-    double *st = dyn;                                        // samples, 1024 + m - 1
-    FT(*stage)[kRec + 1] = (FT(*)[kRec + 1])(dyn + kTileW + m);   // then kRows records
+    double *st = dyn;                                            // samples, 1024 + m - 1
+    double(*stage)[kStageLd] = (double(*)[kStageLd])(dyn + st_len);   // kRowsC rows
 
     if (tid == 0) sm.emax = 0;
     for (int r = tid; r < nw + m - 1; r += kBlock) st[r] = q.t[i0 + r];
-    for (int c = tid; c < q.B * kFD; c += kBlock)
-        sm.g[c / kFD][c % kFD] = q.gproj[(int64_t)l * q.B * kFD + c];
-    __syncthreads();
 
-    // ---- moments (two-pass, population; Sec. 3.2) and compacted positions
+    // ---- compacted positions: thread tid takes windows 4 tid .. 4 tid + 3
     {
-        uint32_t run = tile_off[tile];
-        for (int w0 = 0; w0 < kTileW; w0 += kBlock) {
-            const int w = w0 + tid;
-            const bool in = w < nw;
-            const bool ix = in && E[i0 + w + m] != E[i0 + w + 1];
-            const uint64_t bal = __ballot(ix);
-            if (lane == 0) sm.wsum[wv] = (uint32_t)__popcll(bal);
-            __syncthreads();
-            uint32_t pos = run + (uint32_t)__popcll(bal & lanemask_lt()), tot = 0;
-            for (int x = 0; x < kBlock / kWave; ++x) {
-                if (x < wv) pos += sm.wsum[x];
-                tot += sm.wsum[x];
-            }
-            double is = 0.0;
-            if (ix) {
-                // four partial sums per pass keep the LDS loads independent
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int r = 0;
-                for (; r + 4 <= m; r += 4) {
-                    a0 += st[w + r];
-                    a1 += st[w + r + 1];
-                    a2 += st[w + r + 2];
-                    a3 += st[w + r + 3];
-                }
-                for (; r < m; ++r) a0 += st[w + r];
-                const double mu = ((a0 + a1) + (a2 + a3)) / (double)m;
-                a0 = a1 = a2 = a3 = 0.0;
-                for (r = 0; r + 4 <= m; r += 4) {
-                    const double c0 = st[w + r] - mu, c1 = st[w + r + 1] - mu;
-                    const double c2 = st[w + r + 2] - mu, c3 = st[w + r + 3] - mu;
-                    a0 = fma(c0, c0, a0);
-                    a1 = fma(c1, c1, a1);
-                    a2 = fma(c2, c2, a2);
-                    a3 = fma(c3, c3, a3);
-                }
-                for (; r < m; ++r) {
-                    const double c0 = st[w + r] - mu;
-                    a0 = fma(c0, c0, a0);
-                }
-                const double sg = sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
-                is = 1.0 / sg;
-                if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
-                    // samples differ but sigma underflows or overflows:
-                    // outside the range the library represents; keep the
-                    // window indexed so every count stays consistent
-                    atomicOr(q.bad, 2);
-                    is = 1.0;
-                }
-                q.cell[pos] = (uint32_t)(L.cell_base + i0 + w);
-                q.mu[pos] = mu;
-                q.isig[pos] = is;
-                q.P[pos] = kInfBits;
-            }
-            if (in) {
-                sm.isig[w] = is;
-                sm.kpos[w] = ix ? (int32_t)pos : -1;
-            }
-            run += tot;
-            __syncthreads();
+        bool ix[4];
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * tid + j;
+            ix[j] = w < nw && E[i0 + w + m] != E[i0 + w + 1];
+            c += ix[j];
         }
-        if (tid < kSegs) {
-            int any = 0;
-            for (int w = tid * kSegW; w < min(nw, (tid + 1) * kSegW); ++w) any |= sm.kpos[w] >= 0;
-            sm.seg_any[tid] = any;
+        int x = c;                                               // inclusive wave scan
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int y = __shfl_up(x, off, kWave);
+            if (lane >= off) x += y;
         }
+        if (lane == kWave - 1) sm.wsum[wv] = (uint32_t)x;
         __syncthreads();
+        uint32_t pos = tile_off[tile] + (uint32_t)(x - c);
+        for (int v = 0; v < wv; ++v) pos += sm.wsum[v];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * tid + j;
+            if (w < nw) sm.kpos[w] = ix[j] ? (int32_t)pos++ : -1;
+        }
     }
+    __syncthreads();
 
     // ---- sliding DFT in FP64: thread (segment g, bin b)
     const int b = tid & 15;
@@ -204,17 +301,23 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     const int s0 = g * kSegW;
     const int segn = max(0, min(kSegW, nw - s0));
     const double c = segn > 0 ? st[s0] : 0.0;
+    int any = 0;
     {
-        // largest |t - c| over the segment's samples, for the error bound
+        // does the segment hold an indexed window; the largest |t - c| over
+        // its samples, for the error bound
         double Y = 0.0;
+        for (int r = b; r < segn; r += 16) any |= sm.kpos[s0 + r] >= 0;
         for (int r = b; r < segn + m - 1; r += 16) Y = fmax(Y, fabs(st[s0 + r] - c));
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) Y = fmax(Y, __shfl_xor(Y, off, 16));
+        for (int off = 1; off < 16; off <<= 1) {
+            any |= __shfl_xor(any, off, 16);
+            Y = fmax(Y, __shfl_xor(Y, off, 16));
+        }
         if (b == 0) sm.ymax[g] = (float)(Y * (1.0 + 1e-6)) * (1.0f + 1e-6f);
     }
     double xr = 0.0, xi = 0.0, wcos = 1.0, wsin = 0.0;
     // a segment of constant windows only has no feature to compute
-    const bool own = segn > 0 && b < kp && sm.seg_any[g];
+    const bool own = any && b < kp;
     if (own) {
         const int k = b + 1;
         sincospi(2.0 * (double)k / (double)m, &wsin, &wcos);   // omega = e^{+2 pi i k/m}
@@ -252,15 +355,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         xi = (ai[0] + ai[1]) + (ai[2] + ai[3]);
     }
 
-    const int row = tid >> 2;         // post-processing: four threads per row
-    const int quad = tid & 3;
-    const int pg = row / kChunk, pu = row % kChunk;
-    for (int chunk = 0; chunk < kSegW / kChunk; ++chunk) {
-        // ---- 4 slides of every (segment, bin), into the staging rows
-        for (int u = 0; u < kChunk; ++u) {
-            const int sl = chunk * kChunk + u;
+    float emax = 0.0f;
+    for (int chunk = 0; chunk < kSegW / kSlidesC; ++chunk) {
+        // ---- 8 slides of every (segment, bin), raw bins into the staging rows
+        for (int u = 0; u < kSlidesC; ++u) {
+            const int sl = chunk * kSlidesC + u;
             const int s = s0 + sl;
-            FT *rw = stage[g * kChunk + u];
+            double *rw = stage[g * kSlidesC + u];
             if (sl < segn) {
                 if (own) {
                     if (sl > 0) {
@@ -271,133 +372,34 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
                         xr = fma(a_r, wcos, -(a_i * wsin));
                         xi = fma(a_r, wsin, a_i * wcos);
                     }
-                    const double is = sm.isig[s];
-                    rw[2 * b] = (FT)(xr * is);
-                    rw[2 * b + 1] = (FT)(xi * is);
-                } else if (b < kMaxK - 1) {
-                    rw[2 * b] = (FT)0;
-                    rw[2 * b + 1] = (FT)0;
+                    rw[2 * b] = xr;
+                    rw[2 * b + 1] = xi;
+                } else if (any && b < kMaxK - 1) {
+                    rw[2 * b] = 0.0;
+                    rw[2 * b + 1] = 0.0;
                 }
             }
         }
         __syncthreads();
 
-        // ---- post-processing of the 64 rows
-        const int s = pg * kSegW + chunk * kChunk + pu;
-        const bool valid = s < nw;
-        const int32_t kk = valid ? sm.kpos[s] : -1;
-        const bool indexed = kk >= 0;
-        // constant windows (no cell) skip the arithmetic below
-        float f[kFD];
-        double n2 = 0.0;
-        if (indexed) {
-#pragma unroll
-            for (int x = 0; x < kFD; ++x) f[x] = (float)stage[row][x];
-            // SimHash bits (Sec. 3.4): bit l = [<g_l, F> >= 0], six per
-            // thread; margins and bits go to LDS, so no register array is
-            // indexed at run time and no cross-lane exchange is needed
-            uint32_t sig = 0;
-#pragma unroll
-            for (int h = 0; h < 6; ++h) {
-                const int bt = quad * 6 + h;
-                if (bt < q.B) {
-                    float dot = 0.0f;
-#pragma unroll
-                    for (int x = 0; x < kFD; ++x) dot = fmaf(sm.g[bt][x], f[x], dot);
-                    sm.mg[row][bt] = fabsf(dot);
-                    if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
-                }
-            }
-            sm.sigp[row][quad] = sig;
-            // join record: orthonormal projections of the FP32 copy, FP64 dots
-            float *jr = q.jrec + (int64_t)kk * 8;
-#pragma unroll
-            for (int dd = 0; dd < 2; ++dd) {
-                const int dim = quad + 4 * dd;
-                if (dim < kJoinDims) {
-                    double p = 0.0;
-#pragma unroll
-                    for (int x = 0; x < kFD; ++x) p = fma(q.ujoin[dim * kFD + x], (double)f[x], p);
-                    jr[dim] = (float)p;
-                }
-            }
-            // norm of the FP32 copy (static register indices only)
-            if (quad == 0) {
-#pragma unroll
-                for (int x = 0; x < kFD; ++x) n2 = fma((double)f[x], (double)f[x], n2);
-            }
-        }
-        __syncthreads();                      // margins and bits visible to the quad leader
-        if (indexed && quad == 0) {
-            // Hamming-1 probe order: the `probes` smallest margins among the
-            // d prefix bits, ascending (Sec. 3.4 multi-probe)
-            uint64_t order = 0;
-            uint32_t used = 0;
-            for (int h = 0; h < L.probes; ++h) {
-                int best = -1;
-                float bm = 0.0f;
-                for (int bt = 0; bt < L.depth; ++bt) {
-                    if (used & (1u << bt)) continue;
-                    const float v = sm.mg[row][bt];
-                    if (best < 0 || v < bm) { best = bt; bm = v; }
-                }
-                used |= 1u << best;
-                order |= (uint64_t)best << (5 * h);
-            }
-            const uint32_t sig = sm.sigp[row][0] | sm.sigp[row][1] | sm.sigp[row][2] | sm.sigp[row][3];
-            q.keyw[kk] = (uint64_t)sig | (order << 24);
-            const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
-            q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
-            q.sval[kk] = (uint32_t)kk;
-            float *jr = q.jrec + (int64_t)kk * 8;
-            jr[6] = __uint_as_float((uint32_t)kk);
-            jr[7] = 0.0f;
-            // error bound of the stored features (see file comment): direct
-            // start (4 quarters) + 63 slides in FP64, the multiplication by
-            // 1/sigma, and the rounding to FT; the FP32 copy differs from the
-            // FP64 value by <= u32 |F|, which also bounds the norm used here
-            const double nrm = sqrt(n2) * (1.0 + 1e-6) + 1e-30;
-            const double u64 = 1.1102230246251565e-16;
-            const double ust = sizeof(FT) == 4 ? 5.9604644775390625e-08 : u64;
-            const double Y = (double)sm.ymax[pg];
-            const double Ebin = (6.0 * m * (double)m + 8.0 * kSegW * (m + 2.0) + 2.0 * m) * u64 * Y;
-            const double ecomp = sqrt(2.0 * kp) * Ebin * sm.isig[s] * 1.001;
-            const double estore = (ust + 4.0 * u64) * (nrm + 6e-8 * nrm) * 1.001;
-            const float e = (float)((ecomp + estore) * (1.0 + 1e-6)) * (1.0f + 2.4e-7f) + 1e-30f;
-            stage[row][kSlotErr] = (FT)e;
-            stage[row][kSlotNorm] = (FT)nrm;
-            atomicMax(&sm.emax, __float_as_int(e));
-        }
-        __syncthreads();
-        // ---- whole records out, 16 bytes per thread and store
-        constexpr int kPer = 16 / (int)sizeof(FT);           // FT values per 16 bytes
-        constexpr int kParts = kRec / kPer;                  // 16-byte parts per record
-        for (int flat = tid; flat < kRows * kParts; flat += kBlock) {
-            const int r = flat / kParts, part = flat % kParts;
-            const int sr = (r / kChunk) * kSegW + chunk * kChunk + (r % kChunk);
-            if (sr < nw) {
-                const int32_t kr = sm.kpos[sr];
-                if (kr >= 0) {
-                    const FT *src = &stage[r][part * kPer];
-                    FT *dst = (FT *)q.F + (int64_t)kr * kRec + part * kPer;
-                    if (sizeof(FT) == 8) {
-                        double2 v;
-                        v.x = (double)src[0];
-                        v.y = (double)src[1];
-                        *(double2 *)dst = v;
-                    } else {
-                        float4 v;
-                        v.x = (float)src[0];
-                        v.y = (float)src[1];
-                        v.z = (float)src[kPer > 2 ? 2 : 0];
-                        v.w = (float)src[kPer > 3 ? 3 : 0];
-                        *(float4 *)dst = v;
-                    }
-                }
-            }
+        // ---- one thread per staged window
+        if (tid < kRowsC) {
+            const int row = tid;
+            const int sg = row / kSlidesC;
+            const int s = sg * kSegW + chunk * kSlidesC + (row % kSlidesC);
+            const int32_t kk = s < nw ? sm.kpos[s] : -1;
+            if (kk >= 0)
+                sketch_row<FT>(q, L, l, L.cell_base + i0 + s, st + s, (8 * sg) % m, stage[row],
+                               sm.ymax[sg], kk, gproj + (int64_t)l * q.B * kFD, ujoin, emax);
         }
         __syncthreads();
     }
+    // largest e_i of the tile: one LDS atomic per wavefront
+    int eb = __float_as_int(emax);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) eb = max(eb, __shfl_xor(eb, off, kWave));
+    if (lane == 0 && eb) atomicMax(&sm.emax, eb);
+    __syncthreads();
     if (tid == 0 && sm.emax) atomicMax((int *)&q.emax[l], sm.emax);
 }
 
@@ -451,19 +453,17 @@ void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t nt
 
 void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                    int64_t ntiles, int max_m, hipStream_t s) {
-    // samples (1024 + m - 1 doubles) then the staging rows, sized for the
-    // longest window of the request
-    if (precision == 0) {
-        const size_t dyn = (size_t)(kTileW + max_m) * sizeof(double) +
-                           (size_t)kSegs * kChunk * (kRec + 1) * sizeof(double);
+    // samples (1024 + m - 1 doubles, rounded up to an even count so the
+    // staging rows that follow are 16-byte aligned), then the staging rows,
+    // sized for the longest window of the request
+    const int st_len = (kTileW + max_m + 1) & ~1;
+    const size_t dyn = (size_t)(st_len + kRowsC * kStageLd) * sizeof(double);
+    if (precision == 0)
         hipLaunchKernelGGL((k_sketch<double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off);
-    } else {
-        const size_t dyn = (size_t)(kTileW + max_m) * sizeof(double) +
-                           (size_t)kSegs * kChunk * (kRec + 1) * sizeof(float);
+                           tile_off, st_len, q.gproj, q.ujoin);
+    else
         hipLaunchKernelGGL((k_sketch<float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off);
-    }
+                           tile_off, st_len, q.gproj, q.ujoin);
 }
 
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,

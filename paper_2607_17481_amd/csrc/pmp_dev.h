@@ -21,7 +21,6 @@ constexpr int    kMaxM       = 2048;      // longest window supported
 constexpr int    kTileW      = 1024;      // windows per sketch tile
 constexpr int    kSegW       = 64;        // windows per sliding-DFT segment
 constexpr int    kSegs       = kTileW / kSegW;   // 16 segments, one per 16 lanes
-constexpr int    kChunk      = 4;         // slides between two post-processing steps
 constexpr double kEps0       = 1e-6;      // zero snap (Sec. 3.6)
 constexpr uint64_t kInfBits  = 0x7FF0000000000000ull;   // +inf as FP64 bits
 
