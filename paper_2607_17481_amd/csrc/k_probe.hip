@@ -35,6 +35,7 @@ namespace pmp {
 template <typename FT>
 __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restrict__ bstart,
                                                   int64_t N) {
+    const int64_t k_first = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
     int64_t s = 0;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
     const uint32_t *bb = bstart;
     const FT *fq = (const FT *)q.F;
     if (!done) {
-        const int l = find_len_k(q.len, q.L, k);
+        const int l = find_len_k_wave(q.len, q.L, k_first, k);
         const LenInfo L = q.len[l];
         m = L.m;
         d = L.depth;
@@ -94,19 +95,14 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
                     b = prefix ^ (1u << (d - 1 - bit));
                 }
                 bs = bb[b];
-                if (pr == 0) {
-                    // own bucket: the query sits at slot s; the earlier valid
-                    // entries end just before those within excl of it
-                    cut = s;
-                    while (cut > bs && q.pcell[cut - 1] > lim) --cut;
-                } else {
-                    int64_t lo = bs, hi = bb[b + 1];
-                    while (lo < hi) {
-                        const int64_t mid = (lo + hi) >> 1;
-                        if (q.pcell[mid] <= lim) lo = mid + 1; else hi = mid;
-                    }
-                    cut = lo;
+                // the valid entries (cell <= lim) form a prefix of the bucket;
+                // in the own bucket they all lie before the query's slot s
+                int64_t lo = bs, hi = pr == 0 ? s : (int64_t)bb[b + 1];
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (q.pcell[mid] <= lim) lo = mid + 1; else hi = mid;
                 }
+                cut = lo;
                 const int64_t cnt = cut - bs;
                 j = 0;
                 if (cnt <= 0) { take = 0; continue; }
@@ -126,8 +122,11 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
             const double Pc = bitsd(q.P[kc]);
             const double thr = fmax(Pq, Pc);
             if (thr == 0.0) continue;
-            const float lb = lb_mem<FT>(fq, (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
-            if ((double)lb >= thr) continue;
+            // no bound can prune below +inf: skip the record reads
+            if (thr != INFINITY) {
+                const float lb = lb_mem<FT>(fq, (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
+                if ((double)lb >= thr) continue;
+            }
             has = true;
             pc = kc;
             pic = (int64_t)q.pcell[cs] - cell_base;

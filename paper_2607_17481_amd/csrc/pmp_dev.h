@@ -143,15 +143,43 @@ __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int6
                                               double ia, int64_t b, double mub, double ib, int m) {
 #pragma clang fp contract(off)
     double acc = 0.0;
-    for (int r = lane_id() & (kGroup - 1); r < m; r += kGroup) {
-        const double za = (t[a + r] - mua) * ia;
-        const double zb = (t[b + r] - mub) * ib;
-        const double e = za - zb;
-        acc = fma(e, e, acc);
+    // four terms per lane are loaded before they are summed (in order), so
+    // that a short window costs one memory latency
+    for (int r0 = lane_id() & (kGroup - 1); r0 < m; r0 += 4 * kGroup) {
+        double xa[4], xb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * kGroup;
+            xa[u] = r < m ? t[a + r] : 0.0;
+            xb[u] = r < m ? t[b + r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (r0 + u * kGroup < m) {
+                const double za = (xa[u] - mua) * ia;
+                const double zb = (xb[u] - mub) * ib;
+                const double e = za - zb;
+                acc = fma(e, e, acc);
+            }
+        }
     }
 #pragma unroll
     for (int off = 1; off < kGroup; off <<= 1) acc += __shfl_xor(acc, off, kGroup);
     return sqrt(acc);
+}
+
+// Length index of the indexed positions handled by a wavefront: a scalar
+// binary search for the wavefront's first position (uniform, so it runs on
+// the scalar unit), then a short per-lane step forward.
+__device__ __forceinline__ int find_len_k_wave(const LenInfo *len, int L, int64_t k_first,
+                                               int64_t k) {
+    int lo = 0, hi = L - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (len[mid].kbase <= k_first) lo = mid; else hi = mid - 1;
+    }
+    while (lo + 1 < L && len[lo + 1].kbase <= k) ++lo;
+    return lo;
 }
 
 // Certified lower bound on d_m(q, c) from two stored feature records: the
