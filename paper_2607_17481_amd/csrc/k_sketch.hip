@@ -84,68 +84,29 @@ namespace {
 constexpr int kFD = 2 * (kMaxK - 1);          // 30 feature reals
 constexpr int kRowsC = 128;                   // staged windows per chunk
 constexpr int kSlidesC = kRowsC / kSegs;      // slides per segment per chunk (8)
+constexpr int kGLd = 32;                      // floats per SimHash projection in LDS
 constexpr int kStageLd = 31;                  // doubles per staged row (odd: the
                                               // row threads' 8-byte reads spread
                                               // over all banks)
 
 struct SketchSmem {
     int32_t kpos[kTileW];                     // indexed position, -1: constant window
+    uint8_t rows[kSegW / kSlidesC][kRowsC];   // indexed staging rows of each chunk
+    int32_t nrows[kSegW / kSlidesC];
     float ymax[kSegs];                        // largest |t - c| of each segment
     uint32_t wsum[kBlock / kWave];
     int emax;
 };
 
-// Post-processing of one indexed window (one thread): two-pass moments, the
-// normalized features F = X / sigma written to the record, SimHash bits and
-// the Hamming-1 probe order (Sec. 3.4), the join projections, and the
-// error bound e_i of the stored features.
+// Finishing of one non-constant window (one thread): the normalized
+// features F = X / sigma written to its record, with the norm of their FP32
+// copy and the error bound e_i of the stored features.
 template <typename FT>
-__device__ __forceinline__ void sketch_row(const Req &q, const LenInfo &L, int l, int64_t cell,
-                                           const double *__restrict__ x, int rot,
-                                           const double *__restrict__ X, float Ymax, int kk,
-                                           const float *__restrict__ gl,
-                                           const double *__restrict__ uj, float &emax) {
-    const int m = L.m;
-    // ---- moments, two passes (Sec. 3.2); each sum starts at sample `rot`
-    // and wraps around, so that the row groups of a wavefront, whose windows
-    // lie 64 apart, read different LDS banks
-    double a0 = 0.0, a1 = 0.0;
-    {
-        int r = rot;
-        for (int j = 0; j < m; ++j) {
-            if (j & 1) a1 += x[r]; else a0 += x[r];
-            r = r + 1 == m ? 0 : r + 1;
-        }
-    }
-    const double mu = (a0 + a1) / (double)m;
-    a0 = 0.0;
-    a1 = 0.0;
-    {
-        int r = rot;
-        for (int j = 0; j < m; ++j) {
-            const double c = x[r] - mu;
-            if (j & 1) a1 = fma(c, c, a1); else a0 = fma(c, c, a0);
-            r = r + 1 == m ? 0 : r + 1;
-        }
-    }
-    const double sg = sqrt((a0 + a1) / (double)m);
-    double is = 1.0 / sg;
-    if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
-        // samples differ but sigma underflows or overflows: outside the
-        // range the library represents; the window stays indexed so every
-        // count stays consistent, and the call fails
-        atomicOr(q.bad, 2);
-        is = 1.0;
-    }
-    q.cell[kk] = (uint32_t)cell;
-    q.mu[kk] = mu;
-    q.isig[kk] = is;
-    q.P[kk] = kInfBits;
-
-    // ---- features: scale, store, keep an FP32 copy
+__device__ __forceinline__ void sketch_record(const Req &q, int m, int kprime,
+                                              const double *__restrict__ X, double is,
+                                              float Ymax, int kk, float &emax) {
     FT *rec = (FT *)q.F + (int64_t)kk * kRec;
     float f[kFD];
-    double n2 = 0.0;
 #pragma unroll
     for (int p = 0; p < kFD / 2; ++p) {
         const double vr = X[2 * p] * is, vi = X[2 * p + 1] * is;
@@ -163,63 +124,17 @@ __device__ __forceinline__ void sketch_row(const Req &q, const LenInfo &L, int l
         for (int p = 0; p < 7; ++p)
             *(float4 *)(rec + 4 * p) = make_float4(f[4 * p], f[4 * p + 1], f[4 * p + 2], f[4 * p + 3]);
     }
+    double n2 = 0.0;
 #pragma unroll
-    for (int x2 = 0; x2 < kFD; ++x2) n2 = fma((double)f[x2], (double)f[x2], n2);
-
-    // ---- SimHash bits: bit b = [<g_b, F> >= 0], most significant first
-    uint32_t sig = 0;
-    uint32_t key[kMaxBits];
-#pragma unroll
-    for (int bt = 0; bt < kMaxBits; ++bt) {
-        key[bt] = 0xFFFFFFFFu;
-        if (bt < q.B) {
-            float dot = 0.0f;
-#pragma unroll
-            for (int c = 0; c < kFD; ++c) dot = fmaf(gl[bt * kFD + c], f[c], dot);
-            if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
-            // probe key: the margin |dot| (its order is the order of the
-            // bit patterns) with the bit index in the low five bits
-            if (bt < L.depth) key[bt] = (__float_as_uint(fabsf(dot)) & ~31u) | (uint32_t)bt;
-        }
-    }
-    // ---- Hamming-1 probe order: the `probes` smallest margins among the
-    // d prefix bits, ascending (Sec. 3.4 multi-probe)
-    uint64_t order = 0;
-    for (int h = 0; h < L.probes; ++h) {
-        uint32_t mn = key[0];
-#pragma unroll
-        for (int bt = 1; bt < kMaxBits; ++bt) mn = min(mn, key[bt]);
-        order |= (uint64_t)(mn & 31u) << (5 * h);
-#pragma unroll
-        for (int bt = 0; bt < kMaxBits; ++bt) key[bt] = key[bt] == mn ? 0xFFFFFFFFu : key[bt];
-    }
-    q.keyw[kk] = (uint64_t)sig | (order << 24);
-    const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
-    q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
-    q.sval[kk] = (uint32_t)kk;
-
-    // ---- join record: orthonormal projections of the FP32 copy, FP64 dots
-    float jp[kJoinDims];
-#pragma unroll
-    for (int dm = 0; dm < kJoinDims; ++dm) {
-        double p = 0.0;
-#pragma unroll
-        for (int c = 0; c < kFD; ++c) p = fma(uj[dm * kFD + c], (double)f[c], p);
-        jp[dm] = (float)p;
-    }
-    float4 *jr = (float4 *)(q.jrec + (int64_t)kk * 8);
-    jr[0] = make_float4(jp[0], jp[1], jp[2], jp[3]);
-    jr[1] = make_float4(jp[4], jp[5], __uint_as_float((uint32_t)kk), 0.0f);
-
-    // ---- error bound of the stored features: the direct start (four
-    // quarters) and up to 63 slides in FP64, the scaling by 1/sigma, and the
-    // rounding to FT; the FP32 copy is within u32 |F| of the FP64 value, which
-    // also bounds the norm used here
+    for (int c = 0; c < kFD; ++c) n2 = fma((double)f[c], (double)f[c], n2);
+    // error bound: the direct start (four quarters) and up to 63 slides in
+    // FP64, the scaling by 1/sigma, and the rounding to FT; the FP32 copy is
+    // within u32 |F| of the FP64 value, which also bounds the norm used here
     const double nrm = sqrt(n2) * (1.0 + 1e-6) + 1e-30;
     const double u64 = 1.1102230246251565e-16;
     const double ust = sizeof(FT) == 4 ? 5.9604644775390625e-08 : u64;
     const double Ebin = (6.0 * m * (double)m + 8.0 * kSegW * (m + 2.0) + 2.0 * m) * u64 * (double)Ymax;
-    const double ecomp = sqrt(2.0 * L.kprime) * Ebin * is * 1.001;
+    const double ecomp = sqrt(2.0 * kprime) * Ebin * is * 1.001;
     const double estore = (ust + 4.0 * u64) * (nrm + 6e-8 * nrm) * 1.001;
     const float e = (float)((ecomp + estore) * (1.0 + 1e-6)) * (1.0f + 2.4e-7f) + 1e-30f;
     if (sizeof(FT) == 8) {
@@ -237,18 +152,21 @@ __device__ __forceinline__ void sketch_row(const Req &q, const LenInfo &L, int l
 
 // One block per tile of 1024 consecutive windows of one length.
 //  1. samples into LDS; compacted position of every non-constant window;
+//     two-pass moments of those windows (one thread per window); the list
+//     of non-constant windows of each chunk (below);
 //  2. thread (segment g = tid / 16, bin b = tid % 16) owns bin k = b + 1 of
 //     the 64 windows of segment g: it computes the bin directly at the
 //     segment start (four independent phasor chains, so the sum is not one
 //     long dependent chain) and slides it 63 times, in FP64;
-//  3. every 8 slides the 128 new windows' raw bins are staged in LDS and one
-//     thread per window finishes it (sketch_row).
+//  3. every 8 slides the 128 new windows' raw bins are staged in LDS, and the
+//     non-constant ones among them, packed onto consecutive threads, get
+//     their records one per thread (sketch_record).
+// Keys and join records follow in k_keys, one thread per non-constant
+// window with every lane busy.
 template <typename FT>
 __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__restrict__ E,
                                                       const uint32_t *__restrict__ tile_off,
-                                                      int st_len,
-                                                      const float *__restrict__ gproj,
-                                                      const double *__restrict__ ujoin) {
+                                                      int st_len) {
     extern __shared__ double dyn[];
     __shared__ SketchSmem sm;
     const int64_t tile = blockIdx.x;
@@ -266,6 +184,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
 
     if (tid == 0) sm.emax = 0;
     for (int r = tid; r < nw + m - 1; r += kBlock) st[r] = q.t[i0 + r];
+    // feature slots beyond K' stay zero in every staging row
+    for (int x = tid; x < kRowsC * (kFD - 2 * kp); x += kBlock)
+        stage[x / (kFD - 2 * kp)][2 * kp + x % (kFD - 2 * kp)] = 0.0;
 
     // ---- compacted positions: thread tid takes windows 4 tid .. 4 tid + 3
     {
@@ -294,6 +215,67 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         }
     }
     __syncthreads();
+
+    // ---- moments (two-pass, population; Sec. 3.2), one thread per
+    // non-constant window; four partial sums keep the LDS loads independent
+    for (int w = tid; w < nw; w += kBlock) {
+        const int32_t kk = sm.kpos[w];
+        if (kk < 0) continue;
+        const double *x = st + w;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int r = 0;
+        for (; r + 4 <= m; r += 4) {
+            a0 += x[r];
+            a1 += x[r + 1];
+            a2 += x[r + 2];
+            a3 += x[r + 3];
+        }
+        for (; r < m; ++r) a0 += x[r];
+        const double mu = ((a0 + a1) + (a2 + a3)) / (double)m;
+        a0 = a1 = a2 = a3 = 0.0;
+        for (r = 0; r + 4 <= m; r += 4) {
+            const double c0 = x[r] - mu, c1 = x[r + 1] - mu;
+            const double c2 = x[r + 2] - mu, c3 = x[r + 3] - mu;
+            a0 = fma(c0, c0, a0);
+            a1 = fma(c1, c1, a1);
+            a2 = fma(c2, c2, a2);
+            a3 = fma(c3, c3, a3);
+        }
+        for (; r < m; ++r) {
+            const double c0 = x[r] - mu;
+            a0 = fma(c0, c0, a0);
+        }
+        const double sg = sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
+        double is = 1.0 / sg;
+        if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
+            // samples differ but sigma underflows or overflows: outside the
+            // range the library represents; the window stays indexed so
+            // every count stays consistent, and the call fails
+            atomicOr(q.bad, 2);
+            is = 1.0;
+        }
+        q.cell[kk] = (uint32_t)(L.cell_base + i0 + w);
+        q.mu[kk] = mu;
+        q.isig[kk] = is;
+        q.P[kk] = kInfBits;
+    }
+    // ---- per chunk, the staging rows that hold a non-constant window;
+    // wavefront wv lists chunks 2 wv and 2 wv + 1 (row = segment * 8 + slide)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int chunk = 2 * wv + h;
+        int base = 0;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int row = half * kWave + lane;
+            const int s = (row / kSlidesC) * kSegW + chunk * kSlidesC + (row % kSlidesC);
+            const bool ix = s < nw && sm.kpos[s] >= 0;
+            const uint64_t bal = __ballot(ix);
+            if (ix) sm.rows[chunk][base + __popcll(bal & lanemask_lt())] = (uint8_t)row;
+            base += __popcll(bal);
+        }
+        if (lane == 0) sm.nrows[chunk] = base;
+    }
 
     // ---- sliding DFT in FP64: thread (segment g, bin b)
     const int b = tid & 15;
@@ -358,39 +340,32 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     float emax = 0.0f;
     for (int chunk = 0; chunk < kSegW / kSlidesC; ++chunk) {
         // ---- 8 slides of every (segment, bin), raw bins into the staging rows
-        for (int u = 0; u < kSlidesC; ++u) {
-            const int sl = chunk * kSlidesC + u;
-            const int s = s0 + sl;
-            double *rw = stage[g * kSlidesC + u];
-            if (sl < segn) {
-                if (own) {
-                    if (sl > 0) {
-                        const double ya = st[s - 1] - c;
-                        const double yb = st[s - 1 + m] - c;
-                        const double a_r = xr - ya + yb;
-                        const double a_i = xi;
-                        xr = fma(a_r, wcos, -(a_i * wsin));
-                        xi = fma(a_r, wsin, a_i * wcos);
-                    }
-                    rw[2 * b] = xr;
-                    rw[2 * b + 1] = xi;
-                } else if (any && b < kMaxK - 1) {
-                    rw[2 * b] = 0.0;
-                    rw[2 * b + 1] = 0.0;
+        if (own) {
+            const int u_end = min(kSlidesC, segn - chunk * kSlidesC);
+            for (int u = 0; u < u_end; ++u) {
+                const int s = s0 + chunk * kSlidesC + u;
+                if (s > s0) {
+                    const double ya = st[s - 1] - c;
+                    const double yb = st[s - 1 + m] - c;
+                    const double a_r = xr - ya + yb;
+                    const double a_i = xi;
+                    xr = fma(a_r, wcos, -(a_i * wsin));
+                    xi = fma(a_r, wsin, a_i * wcos);
                 }
+                double *rw = stage[g * kSlidesC + u];
+                rw[2 * b] = xr;
+                rw[2 * b + 1] = xi;
             }
         }
         __syncthreads();
 
-        // ---- one thread per staged window
-        if (tid < kRowsC) {
-            const int row = tid;
+        // ---- the chunk's non-constant windows, one per thread
+        for (int x = tid; x < sm.nrows[chunk]; x += kBlock) {
+            const int row = sm.rows[chunk][x];
             const int sg = row / kSlidesC;
             const int s = sg * kSegW + chunk * kSlidesC + (row % kSlidesC);
-            const int32_t kk = s < nw ? sm.kpos[s] : -1;
-            if (kk >= 0)
-                sketch_row<FT>(q, L, l, L.cell_base + i0 + s, st + s, (8 * sg) % m, stage[row],
-                               sm.ymax[sg], kk, gproj + (int64_t)l * q.B * kFD, ujoin, emax);
+            const int32_t kk = sm.kpos[s];
+            sketch_record<FT>(q, m, kp, stage[row], q.isig[kk], sm.ymax[sg], kk, emax);
         }
         __syncthreads();
     }
@@ -401,6 +376,112 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     if (lane == 0 && eb) atomicMax(&sm.emax, eb);
     __syncthreads();
     if (tid == 0 && sm.emax) atomicMax((int *)&q.emax[l], sm.emax);
+}
+
+// SimHash keys, probe order, bucket sort key and join record of every
+// non-constant window, from its stored record.  Blocks are laid out per
+// length (blk_base), so the length's projections sit in LDS for all threads.
+namespace {
+struct KeysSmem {
+    float g[kMaxBits * kGLd];                 // SimHash projections of the length
+    double uj[kJoinDims * kFD];               // join directions
+};
+}  // namespace
+
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict__ gproj,
+                                                 const double *__restrict__ ujoin) {
+    __shared__ KeysSmem sm;
+    int l;
+    {
+        int lo = 0, hi = q.L - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.len[mid].blk_base <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        l = lo;
+    }
+    const LenInfo L = q.len[l];
+    const int tid = threadIdx.x;
+    for (int x = tid; x < q.B * kGLd; x += kBlock)
+        sm.g[x] = x % kGLd < kFD ? gproj[((int64_t)l * q.B + x / kGLd) * kFD + x % kGLd] : 0.0f;
+    for (int x = tid; x < kJoinDims * kFD; x += kBlock) sm.uj[x] = ujoin[x];
+    __syncthreads();
+    const int64_t j = ((int64_t)blockIdx.x - L.blk_base) * kBlock + tid;
+    if (j >= L.n_index) return;
+    const int64_t kk = L.kbase + j;
+
+    const FT *rec = (const FT *)q.F + kk * kRec;
+    float f[kFD];
+    if (sizeof(FT) == 8) {
+#pragma unroll
+        for (int p = 0; p < kFD / 2; ++p) {
+            const double2 v = *(const double2 *)(rec + 2 * p);
+            f[2 * p] = (float)v.x;
+            f[2 * p + 1] = (float)v.y;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 7; ++p) {
+            const float4 v = *(const float4 *)(rec + 4 * p);
+            f[4 * p] = v.x;
+            f[4 * p + 1] = v.y;
+            f[4 * p + 2] = v.z;
+            f[4 * p + 3] = v.w;
+        }
+        const float2 v = *(const float2 *)(rec + 28);
+        f[28] = v.x;
+        f[29] = v.y;
+    }
+
+    // ---- SimHash bits: bit b = [<g_b, F> >= 0], most significant first;
+    // the margins |<g_b, F>| of the d prefix bits feed a sorted list of the
+    // kProbeSlots smallest (Hamming-1 probe order, Sec. 3.4 multi-probe).
+    // A list entry is the margin's bit pattern (ordered like the margin)
+    // with the bit index in its low five bits.
+    uint32_t sig = 0;
+    uint32_t top[kProbeSlots];
+#pragma unroll
+    for (int h = 0; h < kProbeSlots; ++h) top[h] = 0xFFFFFFFFu;
+#pragma unroll 1
+    for (int bt = 0; bt < q.B; ++bt) {
+        const float *gb = sm.g + bt * kGLd;
+        float dot = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kFD; ++c) dot = fmaf(gb[c], f[c], dot);
+        if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
+        if (bt < L.depth) {
+            uint32_t v = (__float_as_uint(fabsf(dot)) & ~31u) | (uint32_t)bt;
+#pragma unroll
+            for (int h = 0; h < kProbeSlots; ++h) {
+                const uint32_t lo = min(top[h], v);
+                v = max(top[h], v);
+                top[h] = lo;
+            }
+        }
+    }
+    uint64_t order = 0;
+#pragma unroll
+    for (int h = 0; h < kProbeSlots; ++h)
+        if (h < L.probes) order |= (uint64_t)(top[h] & 31u) << (5 * h);
+    q.keyw[kk] = (uint64_t)sig | (order << 24);
+    const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
+    q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
+    q.sval[kk] = (uint32_t)kk;
+
+    // ---- join record: orthonormal projections of the FP32 copy, FP64 dots
+    float jp[kJoinDims];
+#pragma unroll
+    for (int dm = 0; dm < kJoinDims; ++dm) {
+        const double *u = sm.uj + dm * kFD;
+        double p = 0.0;
+#pragma unroll
+        for (int c = 0; c < kFD; ++c) p = fma(u[c], (double)f[c], p);
+        jp[dm] = (float)p;
+    }
+    float4 *jr = (float4 *)(q.jrec + kk * 8);
+    jr[0] = make_float4(jp[0], jp[1], jp[2], jp[3]);
+    jr[1] = make_float4(jp[4], jp[5], __uint_as_float((uint32_t)kk), 0.0f);
 }
 
 // First slot of every bucket from the sorted keys: between two consecutive
@@ -460,10 +541,20 @@ void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_
     const size_t dyn = (size_t)(st_len + kRowsC * kStageLd) * sizeof(double);
     if (precision == 0)
         hipLaunchKernelGGL((k_sketch<double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, st_len, q.gproj, q.ujoin);
+                           tile_off, st_len);
     else
         hipLaunchKernelGGL((k_sketch<float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, st_len, q.gproj, q.ujoin);
+                           tile_off, st_len);
+}
+
+void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s) {
+    if (nblocks <= 0) return;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_keys<double>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj,
+                           q.ujoin);
+    else
+        hipLaunchKernelGGL(k_keys<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj,
+                           q.ujoin);
 }
 
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,

@@ -38,6 +38,7 @@ struct LenInfo {
     int64_t bucket_base;  // first bucket of this length
     int64_t n_index;      // non-constant windows (entries of the directory)
     int64_t tile_base;    // first sketch tile of this length
+    int64_t blk_base;     // first block of this length in k_keys
 };
 
 // Everything a kernel needs to know about one request.
@@ -289,6 +290,7 @@ void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t nt
                         uint32_t *tile_cnt, hipStream_t s);
 void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                    int64_t ntiles, int max_m, hipStream_t s);
+void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s);
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);

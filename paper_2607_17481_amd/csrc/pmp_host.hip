@@ -265,7 +265,7 @@ struct Plan {
     int L = 0;
     std::vector<int> ms;
     std::vector<LenInfo> len;
-    int64_t cells = 0, ntiles = 0, nbuckets = 0, N = 0;
+    int64_t cells = 0, ntiles = 0, nbuckets = 0, N = 0, nkblocks = 0;
     int max_m = 0, len_bits = 0, key_shift = 0, jkey_shift = 0, max_depth = 0;
 };
 
@@ -297,6 +297,7 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
     const int dcap = std::min(o.B, 32 - p.len_bits - 1);
     int64_t kb = 0, bb = 0;
     p.max_depth = 0;
+    p.nkblocks = 0;
     for (int l = 0; l < p.L; ++l) {
         LenInfo &L = p.len[l];
         L.kprime = kprime_of(K, L.m);
@@ -308,6 +309,8 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
         h = std::min(h, std::min(d, o.probe_cap));
         L.probes = h;
         L.kbase = kb;
+        L.blk_base = p.nkblocks;
+        p.nkblocks += (L.n_index + kBlock - 1) / kBlock;
         L.bucket_base = bb;
         kb += L.n_index;
         bb += (int64_t)1 << d;
@@ -742,6 +745,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     // ---- one sketch pass, buckets
     tm.mark(1, s);
     launch_sketch(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, s);
+    launch_keys(o.precision, q, p.nkblocks, s);
     tm.mark(2, s);
     radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
     launch_bucket_bounds(q, N, p.nbuckets, b.bstart, s);
