@@ -88,7 +88,7 @@ typedef struct {
     uint64_t indexed_cells;     /* non-constant windows put in the buckets    */
     uint64_t pass_candidates;   /* candidate inspections of the one pass      */
     uint64_t pass_verified;     /* exact distances of the one pass            */
-    uint64_t join_candidates;   /* pairs inside the join bands                */
+    uint64_t join_candidates;   /* pairs kept by the join's filter            */
     uint64_t join_verified;     /* exact distances of the join                */
     uint64_t hot_buckets;       /* buckets holding more than R entries        */
     int32_t  max_depth;         /* deepest directory (bits)                   */
@@ -103,6 +103,7 @@ typedef struct {
     double   ms_join;
     double   ms_rows;
     uint64_t workspace_bytes;   /* device bytes used by the call              */
+    uint64_t join_pairs;        /* pairs the join's MFMA filter evaluated     */
 } pmp_stats;
 
 /* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),

@@ -1,0 +1,418 @@
+// k_join.hip -- the certificate's exact threshold join, as MFMA tiles.
+//
+// After the one pass the profile is a sound upper bound (Prop. 1); let T be
+// the k-th value the greedy accepts on it.  A pair at distance d <= T has, by
+// Lemma 2, true features within T sqrt(m/2) of each other, hence working
+// vectors G (the stored features as a sum of two bf16 numbers) within
+//   R = T sqrt(m/2) + e'_i + e'_j,     e' >= ||G - F|| (stored record bound
+// plus the FP32 and bf16 roundings).  The join finds every such pair:
+//
+//  * grid: each length's windows get two coordinates, their projections on
+//    the two leading principal directions of that length's features
+//    (orthonormal, so a coordinate moves by at most ||dG||), in cells of
+//    width h >= R; a pair within R lies in adjacent cells;
+//  * tiles: windows sorted by (length, cell) are cut into tiles of 32; a
+//    tile's candidates are the windows of the cells next to its queries' cells
+//    (each a contiguous run of the order), taken 32 at a time;
+//  * filter: for a 32 x 32 tile, <G_q, G_c> comes from six MFMA products in
+//    bf16 with FP32 accumulation (hi.hi + hi.lo + lo.hi), and
+//      ||dG||^2 = |G_q|^2 + |G_c|^2 - 2 <G_q, G_c>
+//    is bounded below with a rigorous rounding margin; a pair is kept unless
+//    that bound exceeds R^2;
+//  * exact: kept pairs pass the exclusion test, the certified Parseval bound
+//    from the stored records (<= T and below one of the two cells) and are
+//    verified with the canonical FP64 distance, lowering both cells.
+//
+// Every unordered pair is examined once: a pair whose other end is itself a
+// query and comes earlier in the order is left to that end's tile (both ends
+// see each other, since cell adjacency is symmetric and the filter is
+// conservative on both sides).
+#include "pmp_dev.h"
+
+namespace pmp {
+
+namespace {
+
+constexpr int kJT = kJoinTile;                // queries / candidates per tile
+constexpr int kQueueHigh = 256;               // kept pairs buffered before the exact stage runs
+constexpr int kQueueCap = kQueueHigh + kJT * kJT;   // room for one more whole tile
+constexpr int kCovSample = 1024;              // windows per length for the principal directions
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
+    union {
+        uint4 u;
+        bf16x8 b;
+    } c;
+    c.u = v;
+    return c.b;
+}
+
+// Lower bound (first index with key >= target) in the sorted keys[lo, hi),
+// by a 64-ary search of the whole wavefront (uniform result).
+__device__ __forceinline__ int64_t wave_lower_bound(const uint32_t *__restrict__ keys, int64_t lo,
+                                                    int64_t hi, uint32_t target) {
+    const int lane = lane_id();
+    while (hi - lo > kWave) {
+        const int64_t step = (hi - lo + kWave - 1) / kWave;
+        const int64_t idx = lo + (int64_t)lane * step;
+        const bool below = idx < hi && keys[idx] < target;
+        const int cnt = __popcll(__ballot(below));
+        if (cnt == 0) return lo;
+        const int64_t nlo = lo + (int64_t)(cnt - 1) * step + 1;
+        const int64_t nhi = min(hi, lo + (int64_t)cnt * step);
+        lo = nlo;
+        hi = nhi;
+    }
+    const int64_t idx = lo + lane;
+    const bool below = idx < hi && keys[idx] < target;
+    return lo + __popcll(__ballot(below));
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// G of one window, in FP64 (hi + lo is exact).
+__device__ __forceinline__ void load_g(const uint4 *__restrict__ op, double g[2 * kMaxK]) {
+#pragma unroll
+    for (int part = 0; part < 4; ++part) {
+        const uint4 h = op[part], w = op[4 + part];
+        const uint32_t hs[4] = {h.x, h.y, h.z, h.w}, ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            g[8 * part + 2 * e] = (double)__uint_as_float(hs[e] << 16) +
+                                  (double)__uint_as_float(ws[e] << 16);
+            g[8 * part + 2 * e + 1] = (double)__uint_as_float(hs[e] & 0xFFFF0000u) +
+                                      (double)__uint_as_float(ws[e] & 0xFFFF0000u);
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------- principal directions
+
+// Mean and second moments of G over an even sample of each length's
+// windows: out[l] = {count, sum[32], sum of products [32 x 32] (upper)}.
+__global__ __launch_bounds__(kBlock) void k_join_cov(Req q, const uint4 *__restrict__ jop,
+                                                     double *__restrict__ out) {
+    __shared__ float rows[64][2 * kMaxK + 1];
+    const int l = blockIdx.x;
+    const LenInfo L = q.len[l];
+    const int64_t n = L.n_index;
+    const int S = (int)min<int64_t>(n, kCovSample);
+    double *o = out + (int64_t)l * (1 + 32 + 32 * 32);
+    // thread -> two (a, b) pairs of the upper triangle, or a mean entry
+    double acc[5] = {0, 0, 0, 0, 0};
+    int pa[5], pb[5];
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+        int p = threadIdx.x + x * kBlock;           // 0 .. 1279: 528 pairs (a <= b < 32), then 32 sums
+        pa[x] = -1;
+        pb[x] = -1;
+        if (p < 528) {
+            int a = 0;
+            while (p >= 32 - a) { p -= 32 - a; ++a; }
+            pa[x] = a;
+            pb[x] = a + p;
+        } else if (p < 528 + 32) {
+            pa[x] = p - 528;
+            pb[x] = 32;                              // the sum entry
+        }
+    }
+    for (int s0 = 0; s0 < S; s0 += 64) {
+        __syncthreads();
+        for (int x = threadIdx.x; x < 64 * 32; x += kBlock) {
+            const int r = x / 32, c = x % 32;
+            float v = 0.0f;
+            if (s0 + r < S) {
+                const int64_t k = L.kbase + (int64_t)(((double)(s0 + r) + 0.5) * (double)n / (double)S);
+                const uint32_t *w = (const uint32_t *)(jop + k * 8);
+                const uint32_t h = w[c / 2], lo = w[16 + c / 2];
+                const uint32_t hb = (c & 1) ? (h & 0xFFFF0000u) : (h << 16);
+                const uint32_t lb = (c & 1) ? (lo & 0xFFFF0000u) : (lo << 16);
+                v = __uint_as_float(hb) + __uint_as_float(lb);
+            }
+            rows[r][c] = v;
+        }
+        if (threadIdx.x < 64) rows[threadIdx.x][32] = 1.0f;
+        __syncthreads();
+        const int rn = min(64, S - s0);
+        for (int r = 0; r < rn; ++r) {
+#pragma unroll
+            for (int x = 0; x < 5; ++x)
+                if (pa[x] >= 0) acc[x] = fma((double)rows[r][pa[x]], (double)rows[r][pb[x]], acc[x]);
+        }
+    }
+    if (threadIdx.x == 0) o[0] = (double)S;
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+        if (pa[x] < 0) continue;
+        if (pb[x] == 32) o[1 + pa[x]] = acc[x];
+        else o[33 + pa[x] * 32 + pb[x]] = acc[x];
+    }
+}
+
+// ------------------------------------------------------------ grid keys
+
+// Sort key (length, cell1, cell2) and value k of every indexed window, and
+// its query flag (cell not yet at 0) for this round.
+__global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__restrict__ gl,
+                                                      const uint4 *__restrict__ jop, int64_t N,
+                                                      int cb, uint32_t *__restrict__ gkey,
+                                                      uint32_t *__restrict__ gval,
+                                                      uint8_t *__restrict__ qf) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= N) return;
+    const int l = find_len_k(q.len, q.L, k);
+    const GridLen &G = gl[l];
+    double g[2 * kMaxK];
+    load_g(jop + k * 8, g);
+    double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2 * (kMaxK - 1); ++c) {
+        p1 = fma(G.u[0][c], g[c], p1);
+        p2 = fma(G.u[1][c], g[c], p2);
+    }
+    const uint32_t top = (1u << cb) - 1u;
+    auto cell = [&](double p) -> uint32_t {
+        const double x = (p - G.qlo) * G.hinv;
+        if (!(x > 0.0)) return 0u;
+        if (x >= (double)top) return top;
+        return (uint32_t)x;
+    };
+    gkey[k] = ((uint32_t)l << (2 * cb)) | (cell(p1) << cb) | cell(p2);
+    gval[k] = (uint32_t)k;
+    qf[k] = q.P[k] != 0ull;
+}
+
+// ------------------------------------------------------------ the tiles
+
+// One wavefront per tile of 32 consecutive sorted windows of one length.
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__restrict__ gl,
+                                                       const uint32_t *__restrict__ gkey,
+                                                       const uint32_t *__restrict__ gval,
+                                                       const uint8_t *__restrict__ qf,
+                                                       const uint4 *__restrict__ jop,
+                                                       const float4 *__restrict__ jmeta,
+                                                       int64_t ntiles, int cb, double T) {
+    __shared__ uint2 queue[kBlock / kWave][kQueueCap];
+    const int wv = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int64_t tile = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
+    if (tile >= ntiles) return;
+    int l;
+    {
+        int lo = 0, hi = q.L - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (gl[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+        }
+        l = lo;
+    }
+    const GridLen &G = gl[l];
+    const LenInfo L = q.len[l];
+    const int m = L.m;
+    const int64_t pbeg = L.kbase, pend = L.kbase + L.n_index;
+    const int64_t p0 = pbeg + (tile - G.tile_base) * kJT;
+    const int i = lane % kJT, hh = lane / kJT;
+    const int64_t pq = p0 + i;
+    const bool validq = pq < pend;
+    const uint32_t kq = validq ? gval[pq] : 0u;
+    const bool isq = validq && qf[kq];
+    if (__ballot(isq) == 0) return;
+
+    // ---- query operands (A) and filter terms
+    bf16x8 aH0, aH1, aL0, aL1;
+    {
+        const uint4 *o = jop + (int64_t)kq * 8;
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        aH0 = as_bf16x8(isq ? o[hh] : z);
+        aH1 = as_bf16x8(isq ? o[2 + hh] : z);
+        aL0 = as_bf16x8(isq ? o[4 + hh] : z);
+        aL1 = as_bf16x8(isq ? o[6 + hh] : z);
+    }
+    float a = INFINITY;                                   // filter term of query i
+    if (isq) {
+        const float4 mt = jmeta[kq];                      // |G|^2, e', |G| bound, 0
+        const double nG2 = (double)mt.x * (1.0 - 0x1.0p-23);
+        double v = 0.5 * (nG2 - G.R2) - G.eps_c * (double)mt.z - 1e-30;
+        v -= 0x1.0p-22 * (fabs(v) + G.nmax2);
+        a = (float)v;
+    }
+    // ---- the rows of adjacent cells
+    const uint32_t cmask = (1u << cb) - 1u;
+    const uint32_t key_q = validq ? gkey[pq] : 0u;
+    const int c1q = (int)((key_q >> cb) & cmask), c2q = (int)(key_q & cmask);
+    const int c1min = wave_min_i(isq ? c1q : INT_MAX), c1max = wave_max_i(isq ? c1q : -1);
+    const uint32_t lbits = (uint32_t)l << (2 * cb);
+    unsigned long long n_pairs = 0, n_kept = 0, n_ver = 0;
+    int qn = 0;                                           // queued pairs (uniform)
+
+    // exact stage for the queued pairs
+    auto flush = [&]() {
+        // the queue is written and read by lanes of this wavefront only
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int base = 0; base < qn; base += kWave) {
+            const int e = base + lane;
+            bool has = false;
+            uint32_t ki = 0, kc = 0;
+            int64_t si = 0, sc = 0;
+            double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0;
+            if (e < qn) {
+                const uint2 pr = queue[wv][e];
+                const int64_t pi_ = pbeg + pr.x, pc_ = pbeg + pr.y;
+                ki = gval[pi_];
+                kc = gval[pc_];
+                if (pc_ != pi_ && !(qf[kc] && pc_ < pi_)) {
+                    si = (int64_t)q.cell[ki] - L.cell_base;
+                    sc = (int64_t)q.cell[kc] - L.cell_base;
+                    const int64_t gap = si > sc ? si - sc : sc - si;
+                    if (gap >= q.excl) {
+                        Pi = bitsd(q.P[ki]);
+                        Pc = bitsd(q.P[kc]);
+                        const double thr = fmin(T, fmax(Pi, Pc));
+                        if (thr > 0.0) {
+                            const float lb = lb_mem<FT>((const FT *)q.F + (int64_t)ki * kRec,
+                                                        (const FT *)q.F + (int64_t)kc * kRec,
+                                                        G.sqrt2m);
+                            if ((double)lb <= T && ((double)lb < Pi || (double)lb < Pc)) {
+                                has = true;
+                                mui = q.mu[ki];
+                                isi = q.isig[ki];
+                                muc = q.mu[kc];
+                                isc = q.isig[kc];
+                            }
+                        }
+                    }
+                }
+            }
+            const uint64_t mask = __ballot(has);
+            n_kept += e < qn;
+            if (mask)
+                verify_proposals(mask, q.t, si, mui, isi, sc, muc, isc, m, [&](double dd) {
+                    ++n_ver;
+                    const unsigned long long db = (unsigned long long)dbits(dd);
+                    if (dd < Pi) atomicMin((unsigned long long *)&q.P[ki], db);
+                    if (dd < Pc) atomicMin((unsigned long long *)&q.P[kc], db);
+                });
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        qn = 0;
+    };
+
+    // walk the candidate runs (one per grid row next to a query's cell) in
+    // tiles of 32; the exact stage runs whenever the queue passes kQueueHigh
+    // and once at the end (one call site)
+    int c1p = max(c1min - 1, 0) - 1;
+    const int c1end = min(c1max + 1, (int)cmask);
+    int64_t c0 = 0, cend = 0;
+    for (;;) {
+        while (c0 >= cend && c1p < c1end) {
+            ++c1p;
+            const bool near = isq && abs(c1q - c1p) <= 1;
+            if (__ballot(near) == 0) continue;
+            const int c2lo = wave_min_i(near ? max(c2q - 1, 0) : INT_MAX);
+            const int c2hi = wave_max_i(near ? min(c2q + 1, (int)cmask) : -1);
+            const uint32_t rk = lbits | ((uint32_t)c1p << cb);
+            c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c2lo);
+            cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c2hi) + 1u);
+        }
+        const bool have = c0 < cend;
+        if (qn > (have ? kQueueHigh : 0)) flush();
+        if (!have) break;
+        const int64_t pc = c0 + i;
+        const bool validc = pc < cend;
+        const uint32_t kc = validc ? gval[pc] : 0u;
+        bf16x8 bH0, bH1, bL0, bL1;
+        float bj = INFINITY;
+        {
+            const uint4 *o = jop + (int64_t)kc * 8;
+            const uint4 z = make_uint4(0, 0, 0, 0);
+            bH0 = as_bf16x8(validc ? o[hh] : z);
+            bH1 = as_bf16x8(validc ? o[2 + hh] : z);
+            bL0 = as_bf16x8(validc ? o[4 + hh] : z);
+            bL1 = as_bf16x8(validc ? o[6 + hh] : z);
+            if (validc) bj = (float)(0.5 * (double)jmeta[kc].x * (1.0 - 0x1.0p-23));
+        }
+        f32x16 acc = {};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bH0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bH1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bL0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bL1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, bH0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, bH1, acc, 0, 0, 0);
+        n_pairs += 16;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            // the rows of the 32 x 32 result this lane holds: 8 (r / 4) + 4 hh + r % 4
+            const float ar = __shfl(a, 8 * (r / 4) + 4 * hh + (r % 4), kWave);
+            const bool keep = acc[r] >= ar + bj;
+            const uint64_t bal = __ballot(keep);
+            if (bal == 0) continue;
+            if (keep) {
+                const int row = 8 * (r / 4) + 4 * hh + (r % 4);
+                queue[wv][qn + __popcll(bal & lanemask_lt())] =
+                    make_uint2((uint32_t)(p0 + row - pbeg), (uint32_t)(pc - pbeg));
+            }
+            qn += __popcll(bal);
+        }
+        c0 += kJT;
+    }
+    // statistics: one atomic per wavefront
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        n_pairs += __shfl_xor(n_pairs, off, kWave);
+        n_kept += __shfl_xor(n_kept, off, kWave);
+        n_ver += __shfl_xor(n_ver, off, kWave);
+    }
+    if (lane == 0) {
+        atomicAdd(&q.counters[C_JOIN_PAIRS], n_pairs);
+        if (n_kept) atomicAdd(&q.counters[C_JOIN_CAND], n_kept);
+        if (n_ver) atomicAdd(&q.counters[C_JOIN_VER], n_ver);
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+size_t join_cov_doubles(int L) { return (size_t)L * (1 + 32 + 32 * 32); }
+
+void launch_join_cov(const Req &q, const uint4 *jop, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_join_cov, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, jop, out);
+}
+
+void launch_grid_keys(const Req &q, const GridLen *gl, const uint4 *jop, int64_t N, int cb,
+                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, hipStream_t s) {
+    if (N > 0)
+        hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, jop, N, cb, gkey,
+                           gval, qf);
+}
+
+void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
+                       const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
+                       const float4 *jmeta, int64_t ntiles, int cb, double T, hipStream_t s) {
+    if (ntiles <= 0) return;
+    const unsigned nb = (unsigned)((ntiles + kBlock / kWave - 1) / (kBlock / kWave));
+    if (precision == 0)
+        hipLaunchKernelGGL(k_join_tiles<double>, dim3(nb), dim3(kBlock), 0, s, q, gl, gkey, gval,
+                           qf, jop, jmeta, ntiles, cb, T);
+    else
+        hipLaunchKernelGGL(k_join_tiles<float>, dim3(nb), dim3(kBlock), 0, s, q, gl, gkey, gval,
+                           qf, jop, jmeta, ntiles, cb, T);
+}
+
+}  // namespace pmp

@@ -378,19 +378,24 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     if (tid == 0 && sm.emax) atomicMax((int *)&q.emax[l], sm.emax);
 }
 
-// SimHash keys, probe order, bucket sort key and join record of every
+// SimHash keys, probe order, bucket sort key and join operands of every
 // non-constant window, from its stored record.  Blocks are laid out per
 // length (blk_base), so the length's projections sit in LDS for all threads.
 namespace {
 struct KeysSmem {
     float g[kMaxBits * kGLd];                 // SimHash projections of the length
-    double uj[kJoinDims * kFD];               // join directions
 };
+
+// bf16 with round to nearest even (finite input), as its 16 bits.
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
 }  // namespace
 
 template <typename FT>
-__global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict__ gproj,
-                                                 const double *__restrict__ ujoin) {
+__global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict__ gproj) {
     __shared__ KeysSmem sm;
     int l;
     {
@@ -405,7 +410,6 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
     const int tid = threadIdx.x;
     for (int x = tid; x < q.B * kGLd; x += kBlock)
         sm.g[x] = x % kGLd < kFD ? gproj[((int64_t)l * q.B + x / kGLd) * kFD + x % kGLd] : 0.0f;
-    for (int x = tid; x < kJoinDims * kFD; x += kBlock) sm.uj[x] = ujoin[x];
     __syncthreads();
     const int64_t j = ((int64_t)blockIdx.x - L.blk_base) * kBlock + tid;
     if (j >= L.n_index) return;
@@ -413,6 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
 
     const FT *rec = (const FT *)q.F + kk * kRec;
     float f[kFD];
+    float erec, nrec;
     if (sizeof(FT) == 8) {
 #pragma unroll
         for (int p = 0; p < kFD / 2; ++p) {
@@ -420,6 +425,9 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
             f[2 * p] = (float)v.x;
             f[2 * p + 1] = (float)v.y;
         }
+        const double2 v = *(const double2 *)(rec + kSlotErr);
+        erec = (float)v.x;
+        nrec = (float)(v.y * (1.0 + 1e-7));
     } else {
 #pragma unroll
         for (int p = 0; p < 7; ++p) {
@@ -429,9 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
             f[4 * p + 2] = v.z;
             f[4 * p + 3] = v.w;
         }
-        const float2 v = *(const float2 *)(rec + 28);
+        const float4 v = *(const float4 *)(rec + 28);
         f[28] = v.x;
         f[29] = v.y;
+        erec = v.z;
+        nrec = v.w;
     }
 
     // ---- SimHash bits: bit b = [<g_b, F> >= 0], most significant first;
@@ -469,19 +479,39 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
     q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
     q.sval[kk] = (uint32_t)kk;
 
-    // ---- join record: orthonormal projections of the FP32 copy, FP64 dots
-    float jp[kJoinDims];
+    // ---- join operands: G = hi + lo, hi = bf16(f), lo = bf16(f - hi); each
+    // component of G is within 2^-17 of the FP32 copy f (relative), and f is
+    // within u32 |F~| of the stored record F~, itself within e of F; so
+    // e' = e + (u32 + 2^-17) |F~| bounds |G - F|
+    uint32_t hw[16], lw[16];
+    double n2 = 0.0;
 #pragma unroll
-    for (int dm = 0; dm < kJoinDims; ++dm) {
-        const double *u = sm.uj + dm * kFD;
-        double p = 0.0;
+    for (int w = 0; w < 16; ++w) {
+        uint32_t hp = 0, lp = 0;
 #pragma unroll
-        for (int c = 0; c < kFD; ++c) p = fma(u[c], (double)f[c], p);
-        jp[dm] = (float)p;
+        for (int e = 0; e < 2; ++e) {
+            const int c = 2 * w + e;
+            const float x = c < kFD ? f[c] : 0.0f;
+            const uint32_t hb = bf16_bits(x);
+            const float xh = __uint_as_float(hb << 16);
+            const uint32_t lb = bf16_bits(x - xh);
+            const double gx = (double)xh + (double)__uint_as_float(lb << 16);
+            n2 = fma(gx, gx, n2);
+            hp |= hb << (16 * e);
+            lp |= lb << (16 * e);
+        }
+        hw[w] = hp;
+        lw[w] = lp;
     }
-    float4 *jr = (float4 *)(q.jrec + kk * 8);
-    jr[0] = make_float4(jp[0], jp[1], jp[2], jp[3]);
-    jr[1] = make_float4(jp[4], jp[5], __uint_as_float((uint32_t)kk), 0.0f);
+    uint4 *jo = q.jop + kk * 8;
+#pragma unroll
+    for (int part = 0; part < 4; ++part) {
+        jo[part] = make_uint4(hw[4 * part], hw[4 * part + 1], hw[4 * part + 2], hw[4 * part + 3]);
+        jo[4 + part] = make_uint4(lw[4 * part], lw[4 * part + 1], lw[4 * part + 2], lw[4 * part + 3]);
+    }
+    const double ep = ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
+    q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),
+                              (float)((double)nrec * (1.0 + 0x1.0p-16)) * (1.0f + 2.4e-7f), 0.0f);
 }
 
 // First slot of every bucket from the sorted keys: between two consecutive
@@ -550,11 +580,9 @@ void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s) {
     if (nblocks <= 0) return;
     if (precision == 0)
-        hipLaunchKernelGGL(k_keys<double>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj,
-                           q.ujoin);
+        hipLaunchKernelGGL(k_keys<double>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj);
     else
-        hipLaunchKernelGGL(k_keys<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj,
-                           q.ujoin);
+        hipLaunchKernelGGL(k_keys<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj);
 }
 
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,

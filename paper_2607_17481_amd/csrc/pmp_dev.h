@@ -16,7 +16,6 @@ constexpr int    kSlotErr    = 30;        // record slot of the error bound e_i
 constexpr int    kSlotNorm   = 31;        // record slot of ||F||
 constexpr int    kMaxBits    = 24;        // SimHash bits B (Sec. 4: B = 24)
 constexpr int    kProbeSlots = 8;         // Hamming-1 probes kept per key word
-constexpr int    kJoinDims   = 6;         // orthonormal projections of a join record
 constexpr int    kMaxM       = 2048;      // longest window supported
 constexpr int    kTileW      = 1024;      // windows per sketch tile
 constexpr int    kSegW       = 64;        // windows per sliding-DFT segment
@@ -61,7 +60,8 @@ struct Req {
     uint64_t *P;           // [N] profile, FP64 bits (atomicMin)
     void    *F;            // [N][kRec] features (float or double)
     uint64_t *keyw;        // [N] key word: signature | probe order << 24
-    float   *jrec;         // [N][8] join record: p1..p6, k bits, 0
+    uint4   *jop;          // [N][8] join operands: 32 bf16 hi, then 32 bf16 lo (G = hi + lo)
+    float4  *jmeta;        // [N] |G|^2, e' >= |G - F|, bound on |G|, 0
     // bucket order (slots)
     uint32_t *skey;        // [N] sort keys
     uint32_t *sval;        // [N] sort values (k)
@@ -69,14 +69,13 @@ struct Req {
     uint32_t *pcell;       // [N] slot -> cell
     uint32_t *inv;         // [N] k -> slot
     const float *gproj;    // [L][B][30] SimHash projections
-    const double *ujoin;   // [kJoinDims][30] orthonormal join directions
     float   *emax;         // [L] largest e_i of each length
     unsigned long long *counters;   // stats counters
     int     *bad;          // raised on inputs the library cannot represent
 };
 
 enum Counter {
-    C_PASS_CAND = 0, C_PASS_VER, C_JOIN_CAND, C_JOIN_VER, C_HOT, C_NCOUNTERS
+    C_PASS_CAND = 0, C_PASS_VER, C_JOIN_CAND, C_JOIN_VER, C_HOT, C_JOIN_PAIRS, C_NCOUNTERS
 };
 
 // ------------------------------------------------------------- helpers
@@ -107,6 +106,17 @@ __device__ __forceinline__ int find_len(const LenInfo *len, int L, int64_t cell)
     return lo;
 }
 
+// Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on
+// XCD b mod 8), each XCD with its own L2.  This maps the launch order onto
+// work order so that every XCD takes one contiguous range of the work, and
+// neighbouring work items, which read neighbouring data, share an L2.
+__device__ __forceinline__ uint32_t xcd_block() {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 // Length index of an indexed position k (slots share the per-length ranges).
 __device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) {
     int lo = 0, hi = L - 1;
@@ -117,10 +127,18 @@ __device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) 
     return lo;
 }
 
-struct JoinLen {
-    float r_filter;     // radius on the join projections
-    float r_key;        // radius used for the key range
-    float prange;       // quantization half-range of the first projection
+constexpr int kJoinTile = 32;             // windows per threshold-join tile
+
+// Per length, one round of the threshold join (k_join.hip).
+struct GridLen {
+    int64_t tile_base;    // first join tile of this length
+    double qlo;           // grid origin of both coordinates
+    double hinv;          // 1 / cell width (0: one cell)
+    double R2;            // squared radius on G (+inf: every pair)
+    double eps_c;         // MFMA dot-product error per unit |G_q| (times the largest |G_c|)
+    double nmax2;         // square of the largest |G|
+    double u[2][2 * (kMaxK - 1)];   // the two principal directions (orthonormal)
+    float sqrt2m;         // sqrt(2/m) (1 + 1e-7)
     float pad;
 };
 
@@ -308,15 +326,14 @@ void launch_select_count(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t 
 void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t need,
                         const uint32_t *off, uint32_t *less, uint64_t *less_val, uint32_t *nless,
                         uint32_t cap, uint32_t *eq, hipStream_t s);
-void launch_join_keys(const Req &q, const float *prange, int64_t N, uint32_t *jk, uint32_t *jv,
-                      hipStream_t s);
-void launch_join_gather(const float *jrec, const uint32_t *jperm, int64_t N, float *jsorted,
-                        hipStream_t s);
-void launch_join_queries(const Req &q, const uint32_t *jinv, int64_t N, uint32_t *jq,
-                         uint32_t *count, hipStream_t s);
-void launch_join(int precision, const Req &q, const float *js, const uint32_t *jkey,
-                 const JoinLen *jl, const uint32_t *jq, int64_t nq, int64_t N, double T,
-                 hipStream_t s);
+// (k_join.hip)
+size_t join_cov_doubles(int L);
+void launch_join_cov(const Req &q, const uint4 *jop, double *out, hipStream_t s);
+void launch_grid_keys(const Req &q, const GridLen *gl, const uint4 *jop, int64_t N, int cb,
+                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, hipStream_t s);
+void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
+                       const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
+                       const float4 *jmeta, int64_t ntiles, int cb, double T, hipStream_t s);
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);

@@ -107,25 +107,64 @@ static double gauss(uint64_t seed, int m, int l, int c) {
 
 constexpr int kFD = 2 * (kMaxK - 1);   // 30 feature reals
 
-// Orthonormal join directions: Gaussian vectors of a stream no length uses
-// (m = 0), made orthonormal by two rounds of modified Gram-Schmidt in FP64.
-static void join_directions(uint64_t seed, double *u /* [kJoinDims][kFD] */) {
-    for (int d = 0; d < kJoinDims; ++d)
-        for (int c = 0; c < kFD; ++c) u[d * kFD + c] = gauss(seed, 0, 32 + d, c);
-    for (int round = 0; round < 2; ++round)
-        for (int d = 0; d < kJoinDims; ++d) {
-            double *v = u + d * kFD;
-            for (int e = 0; e < d; ++e) {
-                const double *w = u + e * kFD;
-                double dot = 0.0;
-                for (int c = 0; c < kFD; ++c) dot += v[c] * w[c];
-                for (int c = 0; c < kFD; ++c) v[c] -= dot * w[c];
-            }
-            double nn = 0.0;
-            for (int c = 0; c < kFD; ++c) nn += v[c] * v[c];
-            nn = std::sqrt(nn);
-            for (int c = 0; c < kFD; ++c) v[c] /= nn;
+// Two leading principal directions of one length's sampled join vectors
+// G (power iteration on their covariance, the second deflated against the
+// first), made orthonormal in FP64.  Any orthonormal pair keeps the
+// threshold join exact; the leading ones make its grid cells selective.
+// c: {count, sum[32], sum of products [32][32] (upper triangle)}.
+static void principal_pair(const double *c, double u[2][kFD]) {
+    const double S = c[0];
+    for (int v = 0; v < 2; ++v)
+        for (int x = 0; x < kFD; ++x) u[v][x] = x == v ? 1.0 : 0.0;
+    if (!(S >= 2.0)) return;
+    static thread_local double C[kFD][kFD];
+    for (int a = 0; a < kFD; ++a)
+        for (int b = a; b < kFD; ++b) {
+            const double v = c[33 + a * 32 + b] / S - (c[1 + a] / S) * (c[1 + b] / S);
+            C[a][b] = v;
+            C[b][a] = v;
         }
+    auto normalize = [](double *x) {
+        double n = 0.0;
+        for (int i = 0; i < kFD; ++i) n += x[i] * x[i];
+        n = std::sqrt(n);
+        if (!(n > 0.0)) return false;
+        for (int i = 0; i < kFD; ++i) x[i] /= n;
+        return true;
+    };
+    auto orth = [](double *x, const double *w) {
+        double d = 0.0;
+        for (int i = 0; i < kFD; ++i) d += x[i] * w[i];
+        for (int i = 0; i < kFD; ++i) x[i] -= d * w[i];
+    };
+    for (int v = 0; v < 2; ++v) {
+        double x[kFD], y[kFD];
+        for (int i = 0; i < kFD; ++i) x[i] = 1.0 + 0.01 * i * (v ? -1.0 : 1.0) + (v && (i & 1) ? -1.0 : 0.0);
+        if (v) orth(x, u[0]);
+        if (!normalize(x)) continue;
+        for (int it = 0; it < 64; ++it) {
+            for (int i = 0; i < kFD; ++i) {
+                double a = 0.0;
+                for (int j = 0; j < kFD; ++j) a += C[i][j] * x[j];
+                y[i] = a;
+            }
+            if (v) orth(y, u[0]);
+            if (!normalize(y)) break;
+            for (int i = 0; i < kFD; ++i) x[i] = y[i];
+        }
+        for (int i = 0; i < kFD; ++i) u[v][i] = x[i];
+    }
+    // exact orthonormality (twice, for rounding)
+    for (int r = 0; r < 2; ++r) {
+        normalize(u[0]);
+        orth(u[1], u[0]);
+        if (!normalize(u[1])) {
+            for (int i = 0; i < kFD; ++i) u[1][i] = 0.0;
+            u[1][std::fabs(u[0][0]) < 0.5 ? 0 : 1] = 1.0;
+            orth(u[1], u[0]);
+            normalize(u[1]);
+        }
+    }
 }
 
 static int kprime_of(int K, int m) {
@@ -328,24 +367,26 @@ struct Bufs {
     uint32_t *flags, *E, *scan_tmp, *tile_off;
     int *bad;
     unsigned long long *counters;
-    float *emax, *gproj, *prange;
-    double *ujoin;
+    float *emax, *gproj;
+    double *cov;
+    GridLen *gl;
     unsigned int *hist;
-    uint32_t *nless, *jq_count;
+    uint32_t *nless;
     RowReq *rows;
     unsigned long long *row_min, *row_arg;
     int64_t *cal_starts;
     double *cal_win;
-    JoinLen *jl;
     // phase 2: sized by the indexed windows N
     uint32_t *cell;
     double *mu, *isig;
     uint64_t *P, *keyw;
     void *F;
-    float *jrec, *jsorted;
+    uint4 *jop;
+    float4 *jmeta;
+    uint8_t *qf;
     uint32_t *skey, *sval, *skey2, *sval2, *pcell, *inv, *bstart;
     void *sort_tmp;
-    uint32_t *jk, *jv, *jk2, *jv2, *jinv, *jq;
+    uint32_t *jk, *jv, *jk2, *jv2;
     uint32_t *sel_cnt, *less_k, *eq_k, *sel_cell;
     uint64_t *less_val;
 };
@@ -363,17 +404,15 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.counters = take<unsigned long long>(a, C_NCOUNTERS);
     b.emax = take<float>(a, p.L);
     b.gproj = take<float>(a, (int64_t)p.L * kMaxBits * kFD);
-    b.prange = take<float>(a, p.L);
-    b.ujoin = take<double>(a, kJoinDims * kFD);
+    b.cov = take<double>(a, (int64_t)join_cov_doubles(p.L));
+    b.gl = take<GridLen>(a, p.L);
     b.hist = take<unsigned int>(a, 2048);
     b.nless = take<uint32_t>(a, 1);
-    b.jq_count = take<uint32_t>(a, 1);
     b.rows = take<RowReq>(a, k);
     b.row_min = take<unsigned long long>(a, k);
     b.row_arg = take<unsigned long long>(a, k);
     b.cal_starts = take<int64_t>(a, 3 * 256);
     b.cal_win = take<double>(a, (int64_t)3 * 256 * p.max_m);
-    b.jl = take<JoinLen>(a, p.L);
 }
 
 static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
@@ -385,8 +424,9 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
     b.P = take<uint64_t>(a, N);
     b.keyw = take<uint64_t>(a, N);
     b.F = a.take((size_t)N * kRec * (precision == 0 ? 8 : 4));
-    b.jrec = take<float>(a, N * 8);
-    b.jsorted = take<float>(a, N * 8);
+    b.jop = take<uint4>(a, N * 8);
+    b.jmeta = take<float4>(a, N);
+    b.qf = take<uint8_t>(a, N);
     b.skey = take<uint32_t>(a, N);
     b.sval = take<uint32_t>(a, N);
     b.skey2 = take<uint32_t>(a, N);
@@ -399,8 +439,6 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
     b.jv = take<uint32_t>(a, N);
     b.jk2 = take<uint32_t>(a, N);
     b.jv2 = take<uint32_t>(a, N);
-    b.jinv = take<uint32_t>(a, N);
-    b.jq = take<uint32_t>(a, N);
     b.sel_cnt = take<uint32_t>(a, select_blocks(N) + 1);
     b.less_k = take<uint32_t>(a, need);
     b.less_val = take<uint64_t>(a, need);
@@ -700,13 +738,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                 for (int c = 0; c < kFD; ++c)
                     g[((size_t)l * o.B + bb) * kFD + c] = (float)gauss(o.seed, p.ms[l], bb, c);
         HIPCHK(hipMemcpyAsync(b.gproj, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice, s));
-        double u[kJoinDims * kFD];
-        join_directions(o.seed, u);
-        HIPCHK(hipMemcpyAsync(b.ujoin, u, sizeof(u), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
-        std::vector<float> pr(p.L);
-        for (int l = 0; l < p.L; ++l) pr[l] = (float)(p.ms[l] / std::sqrt(2.0) * 1.01 + 1.0);
-        HIPCHK(hipMemcpyAsync(b.prange, pr.data(), p.L * sizeof(float), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
     }
     HIPCHK(hipMemsetAsync(b.emax, 0, p.L * sizeof(float), s));
@@ -730,14 +762,14 @@ static int run_pipeline(Run &R, Arena &ar) {
     q.P = b.P;
     q.F = b.F;
     q.keyw = b.keyw;
-    q.jrec = b.jrec;
+    q.jop = b.jop;
+    q.jmeta = b.jmeta;
     q.skey = b.skey;
     q.sval = b.sval;
     q.perm = b.sval;
     q.pcell = b.pcell;
     q.inv = b.inv;
     q.gproj = b.gproj;
-    q.ujoin = b.ujoin;
     q.emax = b.emax;
     q.counters = b.counters;
     q.bad = b.bad;
@@ -774,41 +806,53 @@ static int run_pipeline(Run &R, Arena &ar) {
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
     if (o.certify && N > 0) {
-        launch_join_keys(q, b.prange, N, b.jk, b.jv, s);
-        radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.jkey_shift + p.len_bits, b.sort_tmp, s);
-        launch_join_gather(b.jrec, b.jv, N, b.jsorted, s);
-        launch_invert(b.jv, N, b.jinv, s);
+        // principal directions of each length (once)
+        std::vector<double> cov(join_cov_doubles(p.L));
+        launch_join_cov(q, b.jop, b.cov, s);
+        HIPCHK(hipMemcpyAsync(cov.data(), b.cov, cov.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         std::vector<float> emax(p.L);
         HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        std::vector<JoinLen> jl(p.L);
+        std::vector<GridLen> gl(p.L);
+        int64_t ntiles = 0;
+        for (int l = 0; l < p.L; ++l) {
+            principal_pair(cov.data() + (size_t)l * (1 + 32 + 32 * 32), gl[l].u);
+            gl[l].tile_base = ntiles;
+            ntiles += (p.len[l].n_index + kJoinTile - 1) / kJoinTile;
+        }
+        const int cb = std::min(10, (31 - p.len_bits) / 2);
         for (;;) {
             ++rounds;
             const double Teff = std::max(T, kEps0);
             for (int l = 0; l < p.L; ++l) {
                 const double m = p.ms[l];
-                const double u32 = 5.9604644775390625e-08;
-                const double dp = 2.0 * u32 * (m / std::sqrt(2.0) * 1.01 + 1.0) + 1e-12 * m;
+                const double nmax = m / std::sqrt(2.0) * 1.01 + 1.0;
+                const double epmax = ((double)emax[l] + (5.9604644775390625e-08 + 0x1.0p-17) * nmax * 1.01) *
+                                         (1.0 + 1e-6) + 1e-30;
+                GridLen &G = gl[l];
+                G.qlo = -(nmax * 1.001 + 1e-9);
+                const double hmin = 2.0 * -G.qlo / (double)(1u << cb) * (1.0 + 1e-9);
                 if (std::isinf(Teff)) {
-                    jl[l].r_filter = INFINITY;
-                    jl[l].r_key = INFINITY;
+                    G.R2 = INFINITY;
+                    G.hinv = 0.0;
                 } else {
-                    const double r = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9) + 2.0 * (double)emax[l];
-                    const double rf = (r + 2.0 * std::sqrt((double)kJoinDims) * dp) * (1.0 + 1e-5) + 1e-30;
-                    jl[l].r_filter = (float)rf * (1.0f + 1e-6f);
-                    jl[l].r_key = (float)(rf * (1.0 + 1e-5) + 1e-6 * (1.0 + m));
+                    const double Rr = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9) + 2.0 * epmax;
+                    G.R2 = Rr * Rr * (1.0 + 1e-9);
+                    const double h = std::max((Rr * (1.0 + 1e-9) + 1e-12 * nmax) * (1.0 + 1e-9), hmin);
+                    G.hinv = 1.0 / h;
                 }
-                jl[l].prange = (float)(m / std::sqrt(2.0) * 1.01 + 1.0);
-                jl[l].pad = 0.0f;
+                G.eps_c = 1.6e-5 * nmax;
+                G.nmax2 = nmax * nmax;
+                G.sqrt2m = (float)std::sqrt(2.0 / m) * (1.0f + 1e-7f);
+                G.pad = 0.0f;
             }
-            HIPCHK(hipMemcpyAsync(b.jl, jl.data(), p.L * sizeof(JoinLen), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemsetAsync(b.jq_count, 0, sizeof(uint32_t), s));
-            launch_join_queries(q, b.jinv, N, b.jq, b.jq_count, s);
-            uint32_t nq = 0;
-            HIPCHK(hipMemcpyAsync(&nq, b.jq_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            launch_join(o.precision, q, b.jsorted, b.jk, b.jl, b.jq, nq, N, Teff, s);
+            HIPCHK(hipMemcpyAsync(b.gl, gl.data(), p.L * sizeof(GridLen), hipMemcpyHostToDevice, s));
+            launch_grid_keys(q, b.gl, b.jop, N, cb, b.jk, b.jv, b.qf, s);
+            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + 2 * cb, b.sort_tmp, s);
+            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, ntiles, cb,
+                              Teff, s);
             HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(s));   // gl is rewritten next round
             rc = select_topk(p, b, R.k, s, acc);
             if (rc) return rc;
             if (std::isinf(T)) break;                               // exhaustive
@@ -927,6 +971,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->pass_verified = ctr[C_PASS_VER];
         st->join_candidates = ctr[C_JOIN_CAND];
         st->join_verified = ctr[C_JOIN_VER];
+        st->join_pairs = ctr[C_JOIN_PAIRS];
         st->hot_buckets = ctr[C_HOT];
         st->max_depth = p.max_depth;
         st->threshold = T;

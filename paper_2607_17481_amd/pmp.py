@@ -43,7 +43,7 @@ class Stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_onepass", C.c_double), ("ms_certify", C.c_double),
                 ("ms_sketch", C.c_double), ("ms_sort", C.c_double), ("ms_probe", C.c_double),
                 ("ms_join", C.c_double), ("ms_rows", C.c_double),
-                ("workspace_bytes", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("join_pairs", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("size", "reserved")}
