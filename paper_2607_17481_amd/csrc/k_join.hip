@@ -7,10 +7,13 @@
 //   R = T sqrt(m/2) + e'_i + e'_j,     e' >= ||G - F|| (stored record bound
 // plus the FP32 and bf16 roundings).  The join finds every such pair:
 //
-//  * grid: each length's windows get two coordinates, their projections on
-//    the two leading principal directions of that length's features
-//    (orthonormal, so a coordinate moves by at most ||dG||), in cells of
-//    width h >= R; a pair within R lies in adjacent cells;
+//  * grid: each length's windows get coordinates, the projections of their
+//    FP32 feature copies f on the leading principal directions of that
+//    length's features (orthonormal, so a coordinate moves by at most
+//    ||df|| <= R_f = T sqrt(m/2) + e_i + e_j + u32 (|F~_i| + |F~_j|)); two of
+//    them, in cells of width h >= R_f, place a pair within R_f in adjacent
+//    cells (or one, in finer cells, when R_f is below the two-coordinate
+//    grid's resolution), and all three must differ by at most R_f;
 //  * tiles: windows sorted by (length, cell) are cut into tiles of 32; a
 //    tile's candidates are the windows of the cells next to its queries' cells
 //    (each a contiguous run of the order), taken 32 at a time;
@@ -165,33 +168,43 @@ __global__ __launch_bounds__(kBlock) void k_join_cov(Req q, const uint4 *__restr
 
 // ------------------------------------------------------------ grid keys
 
-// Sort key (length, cell1, cell2) and value k of every indexed window, and
-// its query flag (cell not yet at 0) for this round.
+// Sort key (length, cell1, cell2) and value k of every indexed window, its
+// three principal coordinates, and its query flag (cell not yet at 0) for
+// this round.  With cb2 = 0 the grid
+// has one coordinate only, in finer cells (a band), for radii below the
+// resolution of the two-coordinate grid.
+template <typename FT>
 __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__restrict__ gl,
-                                                      const uint4 *__restrict__ jop, int64_t N,
-                                                      int cb, uint32_t *__restrict__ gkey,
+                                                      int64_t N, int cb1, int cb2,
+                                                      uint32_t *__restrict__ gkey,
                                                       uint32_t *__restrict__ gval,
-                                                      uint8_t *__restrict__ qf) {
+                                                      uint8_t *__restrict__ qf,
+                                                      float4 *__restrict__ gp) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
-    const int l = find_len_k(q.len, q.L, k);
+    const int64_t k_first = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int l = find_len_k_wave(q.len, q.L, k_first, k);
     const GridLen &G = gl[l];
-    double g[2 * kMaxK];
-    load_g(jop + k * 8, g);
-    double p1 = 0.0, p2 = 0.0;
+    // coordinates of the FP32 copy f of the stored record: a coordinate of a
+    // pair moves by at most |f_i - f_j| <= |F_i - F_j| + e_i + e_j + u32 (|F~_i| + |F~_j|)
+    const FT *rec = (const FT *)q.F + k * kRec;
+    double p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
     for (int c = 0; c < 2 * (kMaxK - 1); ++c) {
-        p1 = fma(G.u[0][c], g[c], p1);
-        p2 = fma(G.u[1][c], g[c], p2);
+        const double x = (double)(float)rec[c];
+        p1 = fma(G.u[0][c], x, p1);
+        p2 = fma(G.u[1][c], x, p2);
+        p3 = fma(G.u[2][c], x, p3);
     }
-    const uint32_t top = (1u << cb) - 1u;
-    auto cell = [&](double p) -> uint32_t {
+    gp[k] = make_float4((float)p1, (float)p2, (float)p3, 0.0f);
+    auto cell = [&](double p, int bits) -> uint32_t {
+        const uint32_t top = (1u << bits) - 1u;
         const double x = (p - G.qlo) * G.hinv;
         if (!(x > 0.0)) return 0u;
         if (x >= (double)top) return top;
         return (uint32_t)x;
     };
-    gkey[k] = ((uint32_t)l << (2 * cb)) | (cell(p1) << cb) | cell(p2);
+    gkey[k] = ((uint32_t)l << (cb1 + cb2)) | (cell(p1, cb1) << cb2) | (cb2 ? cell(p2, cb2) : 0u);
     gval[k] = (uint32_t)k;
     qf[k] = q.P[k] != 0ull;
 }
@@ -206,8 +219,11 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
                                                        const uint8_t *__restrict__ qf,
                                                        const uint4 *__restrict__ jop,
                                                        const float4 *__restrict__ jmeta,
-                                                       int64_t ntiles, int cb, double T) {
+                                                       const float4 *__restrict__ gp,
+                                                       int64_t ntiles, int cb1, int cb2,
+                                                       double T) {
     __shared__ uint2 queue[kBlock / kWave][kQueueCap];
+    __shared__ float4 rowt[kBlock / kWave][kJT];          // query coordinates and filter term
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     const int64_t tile = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
@@ -251,12 +267,19 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
         v -= 0x1.0p-22 * (fabs(v) + G.nmax2);
         a = (float)v;
     }
+    if (hh == 0) {
+        const float4 c = isq ? gp[kq] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        rowt[wv][i] = make_float4(c.x, c.y, c.z, a);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+
     // ---- the rows of adjacent cells
-    const uint32_t cmask = (1u << cb) - 1u;
+    const uint32_t mask1 = (1u << cb1) - 1u, mask2 = (1u << cb2) - 1u;
     const uint32_t key_q = validq ? gkey[pq] : 0u;
-    const int c1q = (int)((key_q >> cb) & cmask), c2q = (int)(key_q & cmask);
+    const int c1q = (int)((key_q >> cb2) & mask1), c2q = (int)(key_q & mask2);
     const int c1min = wave_min_i(isq ? c1q : INT_MAX), c1max = wave_max_i(isq ? c1q : -1);
-    const uint32_t lbits = (uint32_t)l << (2 * cb);
+    const uint32_t lbits = (uint32_t)l << (cb1 + cb2);
     unsigned long long n_pairs = 0, n_kept = 0, n_ver = 0;
     int qn = 0;                                           // queued pairs (uniform)
 
@@ -318,18 +341,29 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
     // tiles of 32; the exact stage runs whenever the queue passes kQueueHigh
     // and once at the end (one call site)
     int c1p = max(c1min - 1, 0) - 1;
-    const int c1end = min(c1max + 1, (int)cmask);
+    const int c1end = min(c1max + 1, (int)mask1);
     int64_t c0 = 0, cend = 0;
     for (;;) {
-        while (c0 >= cend && c1p < c1end) {
-            ++c1p;
-            const bool near = isq && abs(c1q - c1p) <= 1;
-            if (__ballot(near) == 0) continue;
-            const int c2lo = wave_min_i(near ? max(c2q - 1, 0) : INT_MAX);
-            const int c2hi = wave_max_i(near ? min(c2q + 1, (int)cmask) : -1);
-            const uint32_t rk = lbits | ((uint32_t)c1p << cb);
-            c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c2lo);
-            cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c2hi) + 1u);
+        if (cb2 == 0) {
+            // one coordinate: the cells next to the queries' cells form a
+            // single run of the order
+            if (c0 >= cend && c1p < c1end) {
+                const uint32_t klo = lbits | (uint32_t)(c1p + 1);
+                c1p = c1end;
+                c0 = wave_lower_bound(gkey, pbeg, pend, klo);
+                cend = wave_lower_bound(gkey, c0, pend, (lbits | (uint32_t)c1end) + 1u);
+            }
+        } else {
+            while (c0 >= cend && c1p < c1end) {
+                ++c1p;
+                const bool near = isq && abs(c1q - c1p) <= 1;
+                if (__ballot(near) == 0) continue;
+                const int c2lo = wave_min_i(near ? max(c2q - 1, 0) : INT_MAX);
+                const int c2hi = wave_max_i(near ? min(c2q + 1, (int)mask2) : -1);
+                const uint32_t rk = lbits | ((uint32_t)c1p << cb2);
+                c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c2lo);
+                cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c2hi) + 1u);
+            }
         }
         const bool have = c0 < cend;
         if (qn > (have ? kQueueHigh : 0)) flush();
@@ -339,6 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
         const uint32_t kc = validc ? gval[pc] : 0u;
         bf16x8 bH0, bH1, bL0, bL1;
         float bj = INFINITY;
+        const float4 gc = validc ? gp[kc] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const bool qc = validc && qf[kc];
         {
             const uint4 *o = jop + (int64_t)kc * 8;
             const uint4 z = make_uint4(0, 0, 0, 0);
@@ -356,18 +392,24 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, bH0, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, bH1, acc, 0, 0, 0);
         n_pairs += 16;
+        // keep (row, candidate) unless the Gram bound or a coordinate rules it
+        // out, or the candidate is a query earlier in the order (its tile
+        // takes the pair), or it is the row itself
+        asm volatile("" ::: "memory");   // read the row table per tile, not once
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             // the rows of the 32 x 32 result this lane holds: 8 (r / 4) + 4 hh + r % 4
-            const float ar = __shfl(a, 8 * (r / 4) + 4 * hh + (r % 4), kWave);
-            const bool keep = acc[r] >= ar + bj;
+            const int row = 8 * (r / 4) + 4 * hh + (r % 4);
+            const float4 rt = rowt[wv][row];
+            const int64_t prow = p0 + row;
+            const bool keep = acc[r] >= rt.w + bj && fabsf(rt.x - gc.x) <= G.rp &&
+                              fabsf(rt.y - gc.y) <= G.rp && fabsf(rt.z - gc.z) <= G.rp &&
+                              pc != prow && !(qc && pc < prow);
             const uint64_t bal = __ballot(keep);
             if (bal == 0) continue;
-            if (keep) {
-                const int row = 8 * (r / 4) + 4 * hh + (r % 4);
+            if (keep)
                 queue[wv][qn + __popcll(bal & lanemask_lt())] =
-                    make_uint2((uint32_t)(p0 + row - pbeg), (uint32_t)(pc - pbeg));
-            }
+                    make_uint2((uint32_t)(prow - pbeg), (uint32_t)(pc - pbeg));
             qn += __popcll(bal);
         }
         c0 += kJT;
@@ -395,24 +437,30 @@ void launch_join_cov(const Req &q, const uint4 *jop, double *out, hipStream_t s)
     hipLaunchKernelGGL(k_join_cov, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, jop, out);
 }
 
-void launch_grid_keys(const Req &q, const GridLen *gl, const uint4 *jop, int64_t N, int cb,
-                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, hipStream_t s) {
-    if (N > 0)
-        hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, jop, N, cb, gkey,
-                           gval, qf);
+void launch_grid_keys(int precision, const Req &q, const GridLen *gl, int64_t N, int cb1,
+                      int cb2, uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
+                      hipStream_t s) {
+    if (N <= 0) return;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_grid_keys<double>, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1,
+                           cb2, gkey, gval, qf, gp);
+    else
+        hipLaunchKernelGGL(k_grid_keys<float>, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1,
+                           cb2, gkey, gval, qf, gp);
 }
 
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
-                       const float4 *jmeta, int64_t ntiles, int cb, double T, hipStream_t s) {
+                       const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
+                       double T, hipStream_t s) {
     if (ntiles <= 0) return;
     const unsigned nb = (unsigned)((ntiles + kBlock / kWave - 1) / (kBlock / kWave));
     if (precision == 0)
         hipLaunchKernelGGL(k_join_tiles<double>, dim3(nb), dim3(kBlock), 0, s, q, gl, gkey, gval,
-                           qf, jop, jmeta, ntiles, cb, T);
+                           qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
     else
         hipLaunchKernelGGL(k_join_tiles<float>, dim3(nb), dim3(kBlock), 0, s, q, gl, gkey, gval,
-                           qf, jop, jmeta, ntiles, cb, T);
+                           qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
 }
 
 }  // namespace pmp

@@ -128,18 +128,19 @@ __device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) 
 }
 
 constexpr int kJoinTile = 32;             // windows per threshold-join tile
+constexpr int kJoinDirs = 3;              // principal directions per length in the join
 
 // Per length, one round of the threshold join (k_join.hip).
 struct GridLen {
     int64_t tile_base;    // first join tile of this length
     double qlo;           // grid origin of both coordinates
     double hinv;          // 1 / cell width (0: one cell)
-    double R2;            // squared radius on G (+inf: every pair)
+    double R2;            // squared radius on the join vectors G (+inf: every pair)
     double eps_c;         // MFMA dot-product error per unit |G_q| (times the largest |G_c|)
     double nmax2;         // square of the largest |G|
-    double u[2][2 * (kMaxK - 1)];   // the two principal directions (orthonormal)
+    double u[kJoinDirs][2 * (kMaxK - 1)];   // principal directions (orthonormal)
     float sqrt2m;         // sqrt(2/m) (1 + 1e-7)
-    float pad;
+    float rp;             // bound on any coordinate difference of a pair within R_f
 };
 
 struct RowReq {
@@ -329,11 +330,13 @@ void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t n
 // (k_join.hip)
 size_t join_cov_doubles(int L);
 void launch_join_cov(const Req &q, const uint4 *jop, double *out, hipStream_t s);
-void launch_grid_keys(const Req &q, const GridLen *gl, const uint4 *jop, int64_t N, int cb,
-                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, hipStream_t s);
+void launch_grid_keys(int precision, const Req &q, const GridLen *gl, int64_t N, int cb1,
+                      int cb2, uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
+                      hipStream_t s);
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
-                       const float4 *jmeta, int64_t ntiles, int cb, double T, hipStream_t s);
+                       const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
+                       double T, hipStream_t s);
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);

@@ -107,28 +107,18 @@ static double gauss(uint64_t seed, int m, int l, int c) {
 
 constexpr int kFD = 2 * (kMaxK - 1);   // 30 feature reals
 
-// Two leading principal directions of one length's sampled join vectors
-// G (power iteration on their covariance, the second deflated against the
-// first), made orthonormal in FP64.  Any orthonormal pair keeps the
-// threshold join exact; the leading ones make its grid cells selective.
+// The kJoinDirs leading principal directions of one length's sampled join
+// vectors G (power iteration on their covariance, each deflated against the
+// ones before), made orthonormal in FP64.  Any orthonormal set keeps the
+// threshold join exact; the leading directions make its cells selective.
 // c: {count, sum[32], sum of products [32][32] (upper triangle)}.
-static void principal_pair(const double *c, double u[2][kFD]) {
+static void principal_dirs(const double *c, double u[kJoinDirs][kFD]) {
     const double S = c[0];
-    for (int v = 0; v < 2; ++v)
-        for (int x = 0; x < kFD; ++x) u[v][x] = x == v ? 1.0 : 0.0;
-    if (!(S >= 2.0)) return;
-    static thread_local double C[kFD][kFD];
-    for (int a = 0; a < kFD; ++a)
-        for (int b = a; b < kFD; ++b) {
-            const double v = c[33 + a * 32 + b] / S - (c[1 + a] / S) * (c[1 + b] / S);
-            C[a][b] = v;
-            C[b][a] = v;
-        }
     auto normalize = [](double *x) {
         double n = 0.0;
         for (int i = 0; i < kFD; ++i) n += x[i] * x[i];
         n = std::sqrt(n);
-        if (!(n > 0.0)) return false;
+        if (!(n > 1e-300)) return false;
         for (int i = 0; i < kFD; ++i) x[i] /= n;
         return true;
     };
@@ -137,33 +127,42 @@ static void principal_pair(const double *c, double u[2][kFD]) {
         for (int i = 0; i < kFD; ++i) d += x[i] * w[i];
         for (int i = 0; i < kFD; ++i) x[i] -= d * w[i];
     };
-    for (int v = 0; v < 2; ++v) {
+    double C[kFD][kFD];
+    for (int a = 0; a < kFD; ++a)
+        for (int b = a; b < kFD; ++b) {
+            const double v = S >= 2.0 ? c[33 + a * 32 + b] / S - (c[1 + a] / S) * (c[1 + b] / S) : 0.0;
+            C[a][b] = v;
+            C[b][a] = v;
+        }
+    for (int v = 0; v < kJoinDirs; ++v) {
         double x[kFD], y[kFD];
-        for (int i = 0; i < kFD; ++i) x[i] = 1.0 + 0.01 * i * (v ? -1.0 : 1.0) + (v && (i & 1) ? -1.0 : 0.0);
-        if (v) orth(x, u[0]);
-        if (!normalize(x)) continue;
-        for (int it = 0; it < 64; ++it) {
-            for (int i = 0; i < kFD; ++i) {
-                double a = 0.0;
-                for (int j = 0; j < kFD; ++j) a += C[i][j] * x[j];
-                y[i] = a;
+        for (int i = 0; i < kFD; ++i) x[i] = 1.0 + 0.37 * ((i * (v + 3)) % 7) - 0.5 * (i % (v + 2));
+        for (int w = 0; w < v; ++w) orth(x, u[w]);
+        if (normalize(x)) {
+            for (int it = 0; it < 64; ++it) {
+                for (int i = 0; i < kFD; ++i) {
+                    double a = 0.0;
+                    for (int j = 0; j < kFD; ++j) a += C[i][j] * x[j];
+                    y[i] = a;
+                }
+                for (int w = 0; w < v; ++w) orth(y, u[w]);
+                if (!normalize(y)) break;
+                for (int i = 0; i < kFD; ++i) x[i] = y[i];
             }
-            if (v) orth(y, u[0]);
-            if (!normalize(y)) break;
-            for (int i = 0; i < kFD; ++i) x[i] = y[i];
+        }
+        // exact orthonormality against the ones before (twice, for rounding);
+        // a degenerate start falls back to a unit vector
+        for (int e = 0;; ++e) {
+            for (int r = 0; r < 2; ++r)
+                for (int w = 0; w < v; ++w) orth(x, u[w]);
+            if (normalize(x)) break;
+            for (int i = 0; i < kFD; ++i) x[i] = i == e ? 1.0 : 0.0;
+        }
+        for (int r = 0; r < 2; ++r) {
+            for (int w = 0; w < v; ++w) orth(x, u[w]);
+            normalize(x);
         }
         for (int i = 0; i < kFD; ++i) u[v][i] = x[i];
-    }
-    // exact orthonormality (twice, for rounding)
-    for (int r = 0; r < 2; ++r) {
-        normalize(u[0]);
-        orth(u[1], u[0]);
-        if (!normalize(u[1])) {
-            for (int i = 0; i < kFD; ++i) u[1][i] = 0.0;
-            u[1][std::fabs(u[0][0]) < 0.5 ? 0 : 1] = 1.0;
-            orth(u[1], u[0]);
-            normalize(u[1]);
-        }
     }
 }
 
@@ -384,6 +383,7 @@ struct Bufs {
     uint4 *jop;
     float4 *jmeta;
     uint8_t *qf;
+    float4 *gp;
     uint32_t *skey, *sval, *skey2, *sval2, *pcell, *inv, *bstart;
     void *sort_tmp;
     uint32_t *jk, *jv, *jk2, *jv2;
@@ -427,6 +427,7 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
     b.jop = take<uint4>(a, N * 8);
     b.jmeta = take<float4>(a, N);
     b.qf = take<uint8_t>(a, N);
+    b.gp = take<float4>(a, N);
     b.skey = take<uint32_t>(a, N);
     b.sval = take<uint32_t>(a, N);
     b.skey2 = take<uint32_t>(a, N);
@@ -816,41 +817,64 @@ static int run_pipeline(Run &R, Arena &ar) {
         std::vector<GridLen> gl(p.L);
         int64_t ntiles = 0;
         for (int l = 0; l < p.L; ++l) {
-            principal_pair(cov.data() + (size_t)l * (1 + 32 + 32 * 32), gl[l].u);
+            principal_dirs(cov.data() + (size_t)l * (1 + 32 + 32 * 32), gl[l].u);
             gl[l].tile_base = ntiles;
             ntiles += (p.len[l].n_index + kJoinTile - 1) / kJoinTile;
         }
+        // two grid coordinates of cb bits each, or, when some length's radius
+        // is below that grid's resolution, one coordinate of cb1 bits
         const int cb = std::min(10, (31 - p.len_bits) / 2);
+        const int cb_fine = 31 - p.len_bits;
         for (;;) {
             ++rounds;
             const double Teff = std::max(T, kEps0);
+            // R: radius on the join vectors G (bf16 pairs); Rf: on the FP32
+            // feature copies f, which place the grid
+            std::vector<double> Rl(p.L), Rf(p.L);
+            bool two_d = true;
             for (int l = 0; l < p.L; ++l) {
                 const double m = p.ms[l];
                 const double nmax = m / std::sqrt(2.0) * 1.01 + 1.0;
                 const double epmax = ((double)emax[l] + (5.9604644775390625e-08 + 0x1.0p-17) * nmax * 1.01) *
                                          (1.0 + 1e-6) + 1e-30;
+                const double efmax = ((double)emax[l] + 5.9604644775390625e-08 * nmax * 1.01) *
+                                         (1.0 + 1e-6) + 1e-30;
+                const double Tr = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9);
+                Rl[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * epmax;
+                Rf[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * efmax;
+                if (p.len[l].n_index > 0 && Rf[l] * (double)(1u << cb) < 2.0 * (nmax * 1.001 + 1e-9))
+                    two_d = false;
+            }
+            const int cb1 = two_d ? cb : cb_fine, cb2 = two_d ? cb : 0;
+            for (int l = 0; l < p.L; ++l) {
+                const double m = p.ms[l];
+                const double nmax = m / std::sqrt(2.0) * 1.01 + 1.0;
                 GridLen &G = gl[l];
                 G.qlo = -(nmax * 1.001 + 1e-9);
-                const double hmin = 2.0 * -G.qlo / (double)(1u << cb) * (1.0 + 1e-9);
-                if (std::isinf(Teff)) {
+                const double hmin = 2.0 * -G.qlo / (double)(1u << cb1) * (1.0 + 1e-9);
+                if (std::isinf(Rl[l])) {
                     G.R2 = INFINITY;
                     G.hinv = 0.0;
                 } else {
-                    const double Rr = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9) + 2.0 * epmax;
-                    G.R2 = Rr * Rr * (1.0 + 1e-9);
-                    const double h = std::max((Rr * (1.0 + 1e-9) + 1e-12 * nmax) * (1.0 + 1e-9), hmin);
+                    G.R2 = Rl[l] * Rl[l] * (1.0 + 1e-9);
+                    // coordinates are computed in FP64 from floats: 1e-12 nmax
+                    // covers their rounding
+                    const double h = std::max((Rf[l] * (1.0 + 1e-9) + 1e-12 * nmax) * (1.0 + 1e-9), hmin);
                     G.hinv = 1.0 / h;
                 }
                 G.eps_c = 1.6e-5 * nmax;
+                // per-pair test on the stored coordinates (floats, each within
+                // 2^-24 nmax of its FP64 value)
+                G.rp = std::isinf(Rf[l]) ? INFINITY
+                                         : (float)((Rf[l] * (1.0 + 1e-6) + 0x1.0p-21 * nmax + 1e-12) * (1.0 + 1e-6));
                 G.nmax2 = nmax * nmax;
                 G.sqrt2m = (float)std::sqrt(2.0 / m) * (1.0f + 1e-7f);
-                G.pad = 0.0f;
             }
             HIPCHK(hipMemcpyAsync(b.gl, gl.data(), p.L * sizeof(GridLen), hipMemcpyHostToDevice, s));
-            launch_grid_keys(q, b.gl, b.jop, N, cb, b.jk, b.jv, b.qf, s);
-            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + 2 * cb, b.sort_tmp, s);
-            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, ntiles, cb,
-                              Teff, s);
+            launch_grid_keys(o.precision, q, b.gl, N, cb1, cb2, b.jk, b.jv, b.qf, b.gp, s);
+            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + cb1 + cb2, b.sort_tmp, s);
+            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntiles,
+                              cb1, cb2, Teff, s);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(s));   // gl is rewritten next round
             rc = select_topk(p, b, R.k, s, acc);
