@@ -233,6 +233,7 @@ def main():
         "pass_verified": last["pass_verified"],
         "join_candidates": last["join_candidates"],
         "join_verified": last["join_verified"],
+        "join_pairs": last["join_pairs"],
         "top1": [res[0].i, res[0].j, res[0].m, res[0].dist] if res else None,
     }
     if not args.no_cpu_baseline:

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
             bool has = false;
             uint32_t ki = 0, kc = 0;
             int64_t si = 0, sc = 0;
-            double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0;
+            double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0, lim = INFINITY;
             if (e < qn) {
                 const uint2 pr = queue[wv][e];
                 const int64_t pi_ = pbeg + pr.x, pc_ = pbeg + pr.y;
@@ -313,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
                                                         G.sqrt2m);
                             if ((double)lb <= T && ((double)lb < Pi || (double)lb < Pc)) {
                                 has = true;
+                                lim = exit_bound(thr);
                                 mui = q.mu[ki];
                                 isi = q.isig[ki];
                                 muc = q.mu[kc];
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
                     const unsigned long long db = (unsigned long long)dbits(dd);
                     if (dd < Pi) atomicMin((unsigned long long *)&q.P[ki], db);
                     if (dd < Pc) atomicMin((unsigned long long *)&q.P[kc], db);
-                });
+                }, lim);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
     bool has = false;
     uint32_t pc = 0;
     int64_t pic = 0;
-    double pPc = 0.0, pmu = 0.0, pis = 0.0;
+    double pPc = 0.0, pmu = 0.0, pis = 0.0, plim = INFINITY;
 
     for (;;) {
         // ---- each lane advances to its next candidate that survives the prune
@@ -128,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
                 if ((double)lb >= thr) continue;
             }
             has = true;
+            plim = exit_bound(thr);
             pc = kc;
             pic = (int64_t)q.pcell[cs] - cell_base;
             pPc = Pc;
@@ -148,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restr
                              if (dd < pPc) atomicMin((unsigned long long *)&q.P[pc], db);
                              has = false;
                              if (Pq == 0.0) done = true;
-                         });
+                         },
+                         plim);
     }
     // stats: one atomic per wave
     unsigned long long a = n_cand, v = n_ver;

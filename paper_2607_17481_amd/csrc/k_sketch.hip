@@ -25,6 +25,9 @@
 // staged in LDS and leave in whole, coalesced rows.
 #include "pmp_dev.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace pmp {
 
 // ------------------------------------------------------- change points
@@ -54,6 +57,13 @@ __device__ __forceinline__ int find_tile_len(const LenInfo *len, int L, int64_t 
         if (len[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// bf16 with round to nearest even (finite input), as its 16 bits.
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
 }
 
 }  // namespace
@@ -135,7 +145,9 @@ __device__ __forceinline__ void sketch_record(const Req &q, int m, int kprime,
     const double ust = sizeof(FT) == 4 ? 5.9604644775390625e-08 : u64;
     const double Ebin = (6.0 * m * (double)m + 8.0 * kSegW * (m + 2.0) + 2.0 * m) * u64 * (double)Ymax;
     const double ecomp = sqrt(2.0 * kprime) * Ebin * is * 1.001;
-    const double estore = (ust + 4.0 * u64) * (nrm + 6e-8 * nrm) * 1.001;
+    // the FP64 two-pass sigma is within (m + 8) u64 of its exact value
+    // (relative), which scales F by as much
+    const double estore = (ust + (4.0 + m + 8.0) * u64) * (nrm + 6e-8 * nrm) * 1.001;
     const float e = (float)((ecomp + estore) * (1.0 + 1e-6)) * (1.0f + 2.4e-7f) + 1e-30f;
     if (sizeof(FT) == 8) {
         double2 v;
@@ -146,6 +158,92 @@ __device__ __forceinline__ void sketch_record(const Req &q, int m, int kprime,
         *(float4 *)(rec + 28) = make_float4(f[28], f[29], e, (float)nrm);
     }
     emax = fmaxf(emax, e);
+}
+
+// Shared first steps of a sketch tile (samples already in LDS): the
+// compacted position k of every non-constant window (thread tid takes
+// windows 4 tid .. 4 tid + 3; a block scan), and the two-pass moments of
+// those windows (Sec. 3.2), one thread per window, with their cell and the
+// initial profile value.  Ends with the block synchronized and kpos final.
+__device__ __forceinline__ void tile_positions_and_moments(
+    const Req &q, const LenInfo &L, int64_t i0, int nw, int64_t tile, const double *st,
+    const uint32_t *__restrict__ E, const uint32_t *__restrict__ tile_off, int32_t *kpos,
+    uint32_t *wsum) {
+    const int m = L.m;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid / kWave;
+    {
+        bool ix[4];
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * tid + j;
+            ix[j] = w < nw && E[i0 + w + m] != E[i0 + w + 1];
+            c += ix[j];
+        }
+        int x = c;                                               // inclusive wave scan
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int y = __shfl_up(x, off, kWave);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) wsum[wv] = (uint32_t)x;
+        __syncthreads();
+        uint32_t pos = tile_off[tile] + (uint32_t)(x - c);
+        for (int v = 0; v < wv; ++v) pos += wsum[v];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int w = 4 * tid + j;
+            if (w < nw) kpos[w] = ix[j] ? (int32_t)pos++ : -1;
+        }
+    }
+    __syncthreads();
+
+    // ---- moments (two-pass, population; Sec. 3.2), one thread per
+    // non-constant window; four partial sums keep the LDS loads independent
+    for (int w = tid; w < nw; w += kBlock) {
+        const int32_t kk = kpos[w];
+        if (kk < 0) continue;
+        const double *x = st + w;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int r = 0;
+        for (; r + 4 <= m; r += 4) {
+            a0 += x[r];
+            a1 += x[r + 1];
+            a2 += x[r + 2];
+            a3 += x[r + 3];
+        }
+        for (; r < m; ++r) a0 += x[r];
+        const double mu = ((a0 + a1) + (a2 + a3)) / (double)m;
+        a0 = a1 = a2 = a3 = 0.0;
+        for (r = 0; r + 4 <= m; r += 4) {
+            const double c0 = x[r] - mu, c1 = x[r + 1] - mu;
+            const double c2 = x[r + 2] - mu, c3 = x[r + 3] - mu;
+            a0 = fma(c0, c0, a0);
+            a1 = fma(c1, c1, a1);
+            a2 = fma(c2, c2, a2);
+            a3 = fma(c3, c3, a3);
+        }
+        for (; r < m; ++r) {
+            const double c0 = x[r] - mu;
+            a0 = fma(c0, c0, a0);
+        }
+        const double sg = sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
+        double is = 1.0 / sg;
+        if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
+            // samples differ but sigma underflows or overflows: outside the
+            // range the library represents; the window stays indexed so
+            // every count stays consistent, and the call fails
+            atomicOr(q.bad, 2);
+            is = 1.0;
+        }
+        q.cell[kk] = (uint32_t)(L.cell_base + i0 + w);
+        q.mu[kk] = mu;
+        q.isig[kk] = is;
+        q.P[kk] = kInfBits;
+    }
+    __syncthreads();
 }
 
 }  // namespace
@@ -188,77 +286,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     for (int x = tid; x < kRowsC * (kFD - 2 * kp); x += kBlock)
         stage[x / (kFD - 2 * kp)][2 * kp + x % (kFD - 2 * kp)] = 0.0;
 
-    // ---- compacted positions: thread tid takes windows 4 tid .. 4 tid + 3
-    {
-        bool ix[4];
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int w = 4 * tid + j;
-            ix[j] = w < nw && E[i0 + w + m] != E[i0 + w + 1];
-            c += ix[j];
-        }
-        int x = c;                                               // inclusive wave scan
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int y = __shfl_up(x, off, kWave);
-            if (lane >= off) x += y;
-        }
-        if (lane == kWave - 1) sm.wsum[wv] = (uint32_t)x;
-        __syncthreads();
-        uint32_t pos = tile_off[tile] + (uint32_t)(x - c);
-        for (int v = 0; v < wv; ++v) pos += sm.wsum[v];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int w = 4 * tid + j;
-            if (w < nw) sm.kpos[w] = ix[j] ? (int32_t)pos++ : -1;
-        }
-    }
-    __syncthreads();
-
-    // ---- moments (two-pass, population; Sec. 3.2), one thread per
-    // non-constant window; four partial sums keep the LDS loads independent
-    for (int w = tid; w < nw; w += kBlock) {
-        const int32_t kk = sm.kpos[w];
-        if (kk < 0) continue;
-        const double *x = st + w;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int r = 0;
-        for (; r + 4 <= m; r += 4) {
-            a0 += x[r];
-            a1 += x[r + 1];
-            a2 += x[r + 2];
-            a3 += x[r + 3];
-        }
-        for (; r < m; ++r) a0 += x[r];
-        const double mu = ((a0 + a1) + (a2 + a3)) / (double)m;
-        a0 = a1 = a2 = a3 = 0.0;
-        for (r = 0; r + 4 <= m; r += 4) {
-            const double c0 = x[r] - mu, c1 = x[r + 1] - mu;
-            const double c2 = x[r + 2] - mu, c3 = x[r + 3] - mu;
-            a0 = fma(c0, c0, a0);
-            a1 = fma(c1, c1, a1);
-            a2 = fma(c2, c2, a2);
-            a3 = fma(c3, c3, a3);
-        }
-        for (; r < m; ++r) {
-            const double c0 = x[r] - mu;
-            a0 = fma(c0, c0, a0);
-        }
-        const double sg = sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
-        double is = 1.0 / sg;
-        if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
-            // samples differ but sigma underflows or overflows: outside the
-            // range the library represents; the window stays indexed so
-            // every count stays consistent, and the call fails
-            atomicOr(q.bad, 2);
-            is = 1.0;
-        }
-        q.cell[kk] = (uint32_t)(L.cell_base + i0 + w);
-        q.mu[kk] = mu;
-        q.isig[kk] = is;
-        q.P[kk] = kInfBits;
-    }
+    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, sm.kpos, sm.wsum);
     // ---- per chunk, the staging rows that hold a non-constant window;
     // wavefront wv lists chunks 2 wv and 2 wv + 1 (row = segment * 8 + slide)
 #pragma unroll
@@ -378,6 +406,172 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     if (tid == 0 && sm.emax) atomicMax((int *)&q.emax[l], sm.emax);
 }
 
+// ------------------------------------------------------- MFMA sketch
+
+// Precision forms 1 and 2: the projection of a block of 32 consecutive
+// windows onto the truncated DFT basis is a dense product
+//   X[w][f] = sum_r y_w[r] B[r][f],   y_w = t[w + .] - mu_w (by Lemma 1 the
+//   shift leaves every bin k >= 1 unchanged),
+//   B[r][2k-2] = cos(2 pi k r / m),  B[r][2k-1] = -sin(2 pi k r / m),
+// done on the matrix cores with FP32 accumulation: form 1 splits y and B
+// into bf16 pairs (hi + lo) and sums hi.hi + hi.lo + lo.hi (FP32-grade
+// results), form 2 uses one bf16 product.  Each window's record carries the
+// derived bound e_i on its error, so the Parseval prune stays a true lower
+// bound; moments stay FP64 (shared with the FP64 form).
+
+// Basis in bf16 pairs, per length: [f (32)][r (m rounded up to 16)], hi
+// then lo.  Computed in FP64 from the exact phase (k r mod m) / m.
+__global__ __launch_bounds__(kBlock) void k_basis(const LenInfo *__restrict__ len, int L,
+                                                  const int64_t *__restrict__ base,
+                                                  uint16_t *__restrict__ bh,
+                                                  uint16_t *__restrict__ bl) {
+    const int l = blockIdx.y;
+    if (l >= L) return;
+    const int m = len[l].m, kp = len[l].kprime;
+    const int mp = (m + 15) & ~15;
+    const int64_t o = base[l];
+    for (int x = blockIdx.x * kBlock + threadIdx.x; x < 32 * mp; x += gridDim.x * kBlock) {
+        const int f = x / mp, r = x % mp;
+        const int k = f / 2 + 1;
+        double v = 0.0;
+        if (f < 2 * kp && r < m) {
+            double sn, cs;
+            sincospi(2.0 * (double)(((int64_t)k * r) % m) / (double)m, &sn, &cs);
+            v = (f & 1) ? -sn : cs;
+        }
+        const float vf = (float)v;
+        const uint32_t h = bf16_bits(vf);
+        bh[o + x] = (uint16_t)h;
+        bl[o + x] = (uint16_t)bf16_bits(vf - __uint_as_float(h << 16));
+    }
+}
+
+namespace {
+constexpr int kMBlk = 32;                     // windows per MFMA block
+typedef __attribute__((ext_vector_type(8))) __bf16 mbf16x8;
+typedef __attribute__((ext_vector_type(16))) float mf32x16;
+
+__device__ __forceinline__ mbf16x8 u4_as_bf16x8(uint4 v) {
+    union {
+        uint4 u;
+        mbf16x8 b;
+    } c;
+    c.u = v;
+    return c.b;
+}
+}  // namespace
+
+template <int kProducts>
+__global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *__restrict__ E,
+                                                        const uint32_t *__restrict__ tile_off,
+                                                        const int64_t *__restrict__ bbase,
+                                                        const uint16_t *__restrict__ bh,
+                                                        const uint16_t *__restrict__ bl) {
+    extern __shared__ double dyn[];
+    __shared__ int32_t kpos[kTileW];
+    __shared__ uint32_t wsum[kBlock / kWave];
+    __shared__ int emax_s;
+    const int64_t tile = blockIdx.x;
+    const int l = find_tile_len(q.len, q.L, tile);
+    const LenInfo L = q.len[l];
+    const int m = L.m;
+    const int mp = (m + 15) & ~15;
+    const int64_t i0 = (tile - L.tile_base) * kTileW;
+    const int nw = (int)min<int64_t>(kTileW, L.W - i0);
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = tid / kWave;
+    double *st = dyn;                              // samples, 1024 + m - 1 (+ zero pad)
+
+    if (tid == 0) emax_s = 0;
+    for (int r = tid; r < nw + mp + kMBlk; r += kBlock) st[r] = r < nw + m - 1 ? q.t[i0 + r] : 0.0;
+    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, wsum);
+
+    const uint4 *Bh = (const uint4 *)(bh + bbase[l]);
+    const uint4 *Bl = (const uint4 *)(bl + bbase[l]);
+    const int i = lane % kMBlk, hh = lane / kMBlk;
+    const double u64 = 1.1102230246251565e-16;
+    // Each window is centred on its own mean, y = t - mu, so that
+    // sum_r |y_r| <= m sigma.  Per component, relative to sum |y_r| |B|:
+    // the float and bf16 roundings of y and B (and the dropped lo.lo), and
+    // the FP32 sums of each 16-sample chunk (3 x 16 products from zero,
+    // rounding up to 2^-23); chunks add up in FP64.
+    const double per = (kProducts == 3 ? 3.1 * 0x1.0p-18 : 2.01 * 0x1.0p-9) + 0x1.0p-24 +
+                       (kProducts * 16) * 0x1.0p-23 * 1.01 + 1e-15;
+    const double ecomp = sqrt(2.0 * L.kprime) * per * (double)m * (1.0 + 1e-6);
+    float emax = 0.0f;
+    for (int blk = wv; blk < kTileW / kMBlk; blk += kBlock / kWave) {
+        const int w0 = blk * kMBlk;
+        if (w0 >= nw) break;
+        const int32_t kw = i < nw - w0 ? kpos[w0 + i] : -1;
+        if (__ballot(kw >= 0) == 0) continue;
+        const double mu = kw >= 0 ? q.mu[kw] : 0.0;
+        const double *x = st + w0 + i + 8 * hh;      // window i, this lane's half of each chunk
+
+        double sum[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) sum[v] = 0.0;
+        for (int r0 = 0; r0 < mp; r0 += 16) {
+            // A: window i, samples r0 + 8 hh .. + 7 (centred, split);  B:
+            // feature i, the same samples
+            mbf16x8 ah, al;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float yf = (float)(x[r0 + e] - mu);
+                const uint32_t h = bf16_bits(yf);
+                ah[e] = __builtin_bit_cast(__bf16, (uint16_t)h);
+                if (kProducts == 3)
+                    al[e] = __builtin_bit_cast(
+                        __bf16, (uint16_t)bf16_bits(yf - __uint_as_float(h << 16)));
+            }
+            const int bo = (i * mp + r0 + 8 * hh) / 8;
+            const mbf16x8 bhv = u4_as_bf16x8(Bh[bo]);
+            mf32x16 acc = {};
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhv, acc, 0, 0, 0);
+            if (kProducts == 3) {
+                const mbf16x8 blv = u4_as_bf16x8(Bl[bo]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) sum[v] += (double)acc[v];
+        }
+        // records: lane i holds feature i of 16 windows (rows 8 (v/4) + 4 hh + v % 4)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int w = w0 + 8 * (v / 4) + 4 * hh + (v % 4);
+            const int32_t kk = w < nw ? kpos[w] : -1;
+            if (__ballot(kk >= 0) == 0) continue;
+            double is = 0.0;
+            if (kk >= 0) is = q.isig[kk];
+            const float fv = (float)(sum[v] * is);
+            float n2 = fv * fv;
+#pragma unroll
+            for (int off = kMBlk / 2; off > 0; off >>= 1) n2 += __shfl_xor(n2, off, kMBlk);
+            if (kk >= 0) {
+                float *rec = (float *)q.F + (int64_t)kk * kRec;
+                // the FP32 sum of 30 squares is within 32 u32 of exact
+                const double nrm = sqrt((double)n2) * (1.0 + 64.0 * 5.9604644775390625e-08) + 1e-30;
+                // ecomp is per unit of sigma / sigma; the stored value adds
+                // its float rounding and the FP64 sigma's (m + 8) u64
+                const double estore = (5.9604644775390625e-08 + (m + 12.0) * u64) * nrm;
+                const float e = (float)((ecomp * (1.0 + 1e-9) + estore) * (1.0 + 1e-5)) * (1.0f + 2.4e-7f) + 1e-30f;
+                float val = i < kFD ? fv : 0.0f;
+                if (i == kSlotErr) val = e;
+                if (i == kSlotNorm) val = (float)nrm * (1.0f + 2.4e-7f);
+                rec[i] = val;
+                emax = fmaxf(emax, e);
+            }
+        }
+    }
+    int eb = __float_as_int(emax);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) eb = max(eb, __shfl_xor(eb, off, kWave));
+    if (lane == 0 && eb) atomicMax(&emax_s, eb);
+    __syncthreads();
+    if (tid == 0 && emax_s) atomicMax((int *)&q.emax[l], emax_s);
+}
+
 // SimHash keys, probe order, bucket sort key and join operands of every
 // non-constant window, from its stored record.  Blocks are laid out per
 // length (blk_base), so the length's projections sit in LDS for all threads.
@@ -386,12 +580,6 @@ struct KeysSmem {
     float g[kMaxBits * kGLd];                 // SimHash projections of the length
 };
 
-// bf16 with round to nearest even (finite input), as its 16 bits.
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
-}
 }  // namespace
 
 template <typename FT>
@@ -575,6 +763,32 @@ void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_
     else
         hipLaunchKernelGGL((k_sketch<float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
                            tile_off, st_len);
+}
+
+int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base) {
+    base.assign(L + 1, 0);
+    for (int l = 0; l < L; ++l) base[l + 1] = base[l] + 32 * (int64_t)((len_host[l].m + 15) & ~15);
+    return base[L];
+}
+
+void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bl,
+                  int max_m, hipStream_t s) {
+    const int mp = (max_m + 15) & ~15;
+    const unsigned gx = (unsigned)std::min<int64_t>((32 * (int64_t)mp + kBlock - 1) / kBlock, 64);
+    hipLaunchKernelGGL(k_basis, dim3(gx, (unsigned)L), dim3(kBlock), 0, s, len, L, base, bh, bl);
+}
+
+void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
+                        int64_t ntiles, int max_m, const int64_t *bbase, const uint16_t *bh,
+                        const uint16_t *bl, hipStream_t s) {
+    // samples of the tile, padded with zeros for the last block's reads
+    const size_t dyn = (size_t)(kTileW + ((max_m + 15) & ~15) + kMBlk) * sizeof(double);
+    if (precision == 1)
+        hipLaunchKernelGGL((k_sketch_mfma<3>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                           tile_off, bbase, bh, bl);
+    else
+        hipLaunchKernelGGL((k_sketch_mfma<1>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                           tile_off, bbase, bh, bl);
 }
 
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace pmp {
 
 // ------------------------------------------------------------ constants
@@ -160,7 +162,8 @@ struct RowReq {
 constexpr int kGroup = 16;
 
 __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
-                                              double ia, int64_t b, double mub, double ib, int m) {
+                                              double ia, int64_t b, double mub, double ib, int m,
+                                              double lim2 = INFINITY) {
 #pragma clang fp contract(off)
     double acc = 0.0;
     // four terms per lane are loaded before they are summed (in order), so
@@ -182,10 +185,26 @@ __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int6
                 acc = fma(e, e, acc);
             }
         }
+        // early exit: the partial sums only grow (every term is >= 0 and
+        // rounding is monotone), so once their total reaches lim2 the
+        // finished sum would too; the group decides together (all its lanes
+        // compute the same total)
+        if (lim2 != INFINITY && (r0 | (kGroup - 1)) + 1 + 3 * kGroup < m) {
+            double sp = acc;
+#pragma unroll
+            for (int off = 1; off < kGroup; off <<= 1) sp += __shfl_xor(sp, off, kGroup);
+            if (sp >= lim2) return INFINITY;
+        }
     }
 #pragma unroll
     for (int off = 1; off < kGroup; off <<= 1) acc += __shfl_xor(acc, off, kGroup);
     return sqrt(acc);
+}
+
+// Squared bound for group_zdist's early exit: a sum that reaches it has a
+// computed root >= thr (the factor covers the roundings of thr^2 and sqrt).
+__device__ __forceinline__ double exit_bound(double thr) {
+    return thr == INFINITY ? INFINITY : thr * thr * (1.0 + 8.0 * 1.1102230246251565e-16);
 }
 
 // Length index of the indexed positions handled by a wavefront: a scalar
@@ -253,12 +272,15 @@ __device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__r
 
 // Verification of the proposals of a wavefront.  Every lane whose bit is set
 // in `mask` has a proposal (a, b: window starts; mua, ia, mub, ib: moments;
-// m).  The proposals are taken four at a time, one per 16-lane group;
-// `on_result(d)` runs on the proposing lane with its snapped distance.
+// m; lim2: the squared distance at or above which the result is of no use,
+// see exit_bound).  The proposals are taken four at a time, one per 16-lane
+// group; `on_result(d)` runs on the proposing lane with its snapped distance
+// (+inf when the sum stopped early).
 template <typename F>
 __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__restrict__ t,
                                                  int64_t a, double mua, double ia, int64_t b,
-                                                 double mub, double ib, int m, F &&on_result) {
+                                                 double mub, double ib, int m, F &&on_result,
+                                                 double lim2 = INFINITY) {
     const int lane = lane_id();
     const int grp = lane / kGroup;
     while (mask) {
@@ -279,9 +301,10 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__
         const int64_t gb = __shfl(b, my, kWave);
         const double gmua = __shfl(mua, my, kWave), gia = __shfl(ia, my, kWave);
         const double gmub = __shfl(mub, my, kWave), gib = __shfl(ib, my, kWave);
+        const double glim = __shfl(lim2, my, kWave);
         int gm = __shfl(m, my, kWave);
         if (src[grp] < 0) gm = 0;
-        const double d = snap(group_zdist(t, ga, gmua, gia, gb, gmub, gib, gm));
+        const double d = snap(group_zdist(t, ga, gmua, gia, gb, gmub, gib, gm, glim));
         // hand each result back to its proposing lane
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -310,6 +333,12 @@ void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t nt
 void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                    int64_t ntiles, int max_m, hipStream_t s);
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s);
+int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base);
+void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bl,
+                  int max_m, hipStream_t s);
+void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
+                        int64_t ntiles, int max_m, const int64_t *bbase, const uint16_t *bh,
+                        const uint16_t *bl, hipStream_t s);
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);

@@ -369,6 +369,8 @@ struct Bufs {
     float *emax, *gproj;
     double *cov;
     GridLen *gl;
+    int64_t *bbase;            // MFMA sketch basis: offsets per length, then hi / lo tables
+    uint16_t *bh, *bl;
     unsigned int *hist;
     uint32_t *nless;
     RowReq *rows;
@@ -405,6 +407,13 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.emax = take<float>(a, p.L);
     b.gproj = take<float>(a, (int64_t)p.L * kMaxBits * kFD);
     b.cov = take<double>(a, (int64_t)join_cov_doubles(p.L));
+    {
+        std::vector<int64_t> base;
+        const int64_t ne = basis_elems(p.len.data(), p.L, base);
+        b.bbase = take<int64_t>(a, p.L + 1);
+        b.bh = take<uint16_t>(a, ne);
+        b.bl = take<uint16_t>(a, ne);
+    }
     b.gl = take<GridLen>(a, p.L);
     b.hist = take<unsigned int>(a, 2048);
     b.nless = take<uint32_t>(a, 1);
@@ -776,8 +785,19 @@ static int run_pipeline(Run &R, Arena &ar) {
     q.bad = b.bad;
 
     // ---- one sketch pass, buckets
+    std::vector<int64_t> bbase;             // lives until the call ends (async copy)
+    basis_elems(p.len.data(), p.L, bbase);
     tm.mark(1, s);
-    launch_sketch(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, s);
+    if (o.precision == 0) {
+        launch_sketch(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, s);
+    } else {
+        // precision forms: the projection on the matrix cores
+        HIPCHK(hipMemcpyAsync(b.bbase, bbase.data(), (p.L + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+        launch_basis(b.len, p.L, b.bbase, b.bh, b.bl, p.max_m, s);
+        launch_sketch_mfma(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, b.bbase, b.bh, b.bl,
+                           s);
+    }
     launch_keys(o.precision, q, p.nkblocks, s);
     tm.mark(2, s);
     radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
