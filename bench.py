@@ -146,6 +146,66 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
+SERVING_DEFAULT = {"requests": 96, "n_lo": 10_000, "n_hi": 500_000, "slots": 4,
+                   "hbm_budget_gb": 96}
+
+
+def serving_run(precision, reqs, series, rate, slots, budget):
+    """Open loop: each request is submitted at its Poisson arrival time; the
+    server admits it when a slot and HBM budget are free.  Latency is the
+    library's clock from submission to results in host memory."""
+    import threading
+    from paper_2607_17481_amd import pmp
+    opts = pmp.options(precision=precision)
+    results = [None] * len(reqs)
+    with pmp.Server(0, budget, slots=slots) as srv:
+        ids = []
+        done = threading.Event()
+
+        def collect():
+            i = 0
+            while i < len(reqs):
+                if i < len(ids):
+                    results[i] = srv.wait(ids[i])[1]
+                    i += 1
+                else:
+                    time.sleep(0.001)
+            done.set()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for r, t in zip(reqs, series):
+            delay = r.arrival_s / rate - (time.perf_counter() - t0) if rate else 0.0
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(t, r.m_min, r.m_max, r.k, r.exclusion, 16, opts))
+        th.join()
+    lat = np.array([tm["end_s"] - tm["submit_s"] for tm in results])
+    span = max(tm["end_s"] for tm in results) - min(tm["submit_s"] for tm in results)
+    cells = sum(r.cells for r in reqs)
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "req_per_s": len(reqs) / span, "samples_lengths_per_s": cells / span}
+
+
+def serving_bench(cfg):
+    """Heterogeneous requests (Wafer-like / ECG-like, lengths log-uniform,
+    length intervals of 8-64 lengths starting at 16-512) at 0.8 x the plain
+    FP64 capacity, FP64 form and FP32 (MFMA) form."""
+    reqs = synth.serving_requests(cfg["requests"], 1.0, cfg["n_lo"], cfg["n_hi"])
+    series = [r.series() for r in reqs]
+    budget = cfg["hbm_budget_gb"] << 30
+    # capacity: everything submitted at once (closed loop), FP64 form
+    cap = serving_run(0, reqs, series, 0.0, cfg["slots"], budget)["req_per_s"]
+    rate = 0.8 * cap
+    out = {"requests": len(reqs), "n_range": [cfg["n_lo"], cfg["n_hi"]], "slots": cfg["slots"],
+           "hbm_budget_gb": cfg["hbm_budget_gb"], "capacity_req_per_s_fp64": cap,
+           "arrival_rate_req_per_s": rate}
+    for name, prec in (("fp64", 0), ("fp32", 1)):
+        out[name] = serving_run(prec, reqs, series, rate, cfg["slots"], budget)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +214,8 @@ def main():
     ap.add_argument("--workload", default="wafer5m", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the copy kernel that scales the HBM counters")
     args = ap.parse_args()
@@ -236,6 +298,29 @@ def main():
         "join_pairs": last["join_pairs"],
         "top1": [res[0].i, res[0].j, res[0].m, res[0].dist] if res else None,
     }
+    if not args.no_forms:
+        # the same workload in the other precision forms (exact results equal)
+        forms = {}
+        for name, prec in PREC.items():
+            if prec == PREC[args.precision]:
+                continue
+            o2 = pmp.options(m_step=step, precision=prec)
+            pmp.run_device(td, m_min, m_max, k, excl, 16, o2, ws, stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                r2, s2 = pmp.run_device(td, m_min, m_max, k, excl, 16, o2, ws, stream)
+            torch.cuda.synchronize()
+            el2 = time.perf_counter() - t1
+            forms[name] = {"ms_per_step": el2 * 1e3 / args.steps, "value": cells * args.steps / el2,
+                           "same_top_k": [(x.i, x.m) for x in r2] == [(x.i, x.m) for x in res],
+                           "max_rel_dist_err": max([abs(a.dist - b.dist) / max(b.dist, 1e-300)
+                                                    for a, b in zip(r2, res)] + [0.0])}
+        line["precision_forms"] = forms
+    if not args.no_serving:
+        del ws
+        torch.cuda.empty_cache()
+        line["serving"] = serving_bench(SERVING_DEFAULT)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.workload)
     print(json.dumps(line), flush=True)
