@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_select_emit(const uint64_t *__restri
 // Pass 1 (find_min = 1): out_min[c] = min over valid j of the snapped
 // distance.  Pass 2: out_arg[c] = smallest valid j whose snapped distance
 // equals req[c].target.  Constant windows are not indexed and never scanned.
-// Each 16-lane group takes every (groups)-th window of the length.
+// Each group of kGroup lanes takes every (groups)-th window of the length.
 __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict__ rr, int find_min,
                                                  unsigned long long *__restrict__ out_min,
                                                  unsigned long long *__restrict__ out_arg) {

@@ -20,7 +20,7 @@
 //
 // GPU mapping: one lane per query searches its candidates (lane-parallel
 // bound tests); the exact distances of the proposals (one per lane per round)
-// are computed four at a time by the 16-lane groups of the wavefront, with
+// are computed kPerRound at a time by the lane groups of the wavefront, with
 // contiguous loads (group_zdist).
 //
 // One departure from the paper: a query stops once its own cell reaches 0

@@ -152,14 +152,15 @@ struct RowReq {
     uint64_t target;    // pass 2: FP64 bits of the value whose smallest j is wanted
 };
 
-// The canonical exact distance, computed by a group of 16 consecutive lanes
-// (four groups per wavefront, each with its own pair): lane g of the group
-// sums the terms r = g, g+16, g+32, ... in ascending order, then a butterfly
-// over the 16 lanes adds the partial sums.  Every kernel that writes,
+// The canonical exact distance, computed by a group of kGroup consecutive
+// lanes (kPerRound groups per wavefront, each with its own pair): lane g of
+// the group sums the terms r = g, g + kGroup, ... in ascending order, then a
+// butterfly over the group adds the partial sums.  Every kernel that writes,
 // compares or reports a distance calls this function, so they all agree bit
 // for bit; every step is symmetric in (a, b), so d(a, b) == d(b, a).  Loads
 // of a group are contiguous.  All 64 lanes of the wavefront must call it.
-constexpr int kGroup = 16;
+constexpr int kGroup = 8;                 // lanes per exact distance
+constexpr int kPerRound = kWave / kGroup; // distances per wavefront round
 
 __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
                                               double ia, int64_t b, double mub, double ib, int m,
@@ -273,8 +274,8 @@ __device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__r
 // Verification of the proposals of a wavefront.  Every lane whose bit is set
 // in `mask` has a proposal (a, b: window starts; mua, ia, mub, ib: moments;
 // m; lim2: the squared distance at or above which the result is of no use,
-// see exit_bound).  The proposals are taken four at a time, one per 16-lane
-// group; `on_result(d)` runs on the proposing lane with its snapped distance
+// see exit_bound).  The proposals are taken kPerRound at a time, one per
+// group of kGroup lanes; `on_result(d)` runs on the proposing lane with its snapped distance
 // (+inf when the sum stopped early).
 template <typename F>
 __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__restrict__ t,
@@ -284,11 +285,11 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__
     const int lane = lane_id();
     const int grp = lane / kGroup;
     while (mask) {
-        // the next four proposing lanes, in lane order
-        int src[4];
+        // the next kPerRound proposing lanes, in lane order
+        int src[kPerRound];
         int cnt = 0;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < kPerRound; ++g) {
             src[g] = -1;
             if (mask) {
                 src[g] = __ffsll((unsigned long long)mask) - 1;
@@ -296,18 +297,23 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__
                 ++cnt;
             }
         }
-        const int my = src[grp] < 0 ? src[0] : src[grp];
+        int mys = src[0];
+#pragma unroll
+        for (int g = 1; g < kPerRound; ++g)
+            if (grp == g && src[g] >= 0) mys = src[g];
+        const bool live = grp == 0 || (grp < cnt);
+        const int my = mys;
         const int64_t ga = __shfl(a, my, kWave);
         const int64_t gb = __shfl(b, my, kWave);
         const double gmua = __shfl(mua, my, kWave), gia = __shfl(ia, my, kWave);
         const double gmub = __shfl(mub, my, kWave), gib = __shfl(ib, my, kWave);
         const double glim = __shfl(lim2, my, kWave);
         int gm = __shfl(m, my, kWave);
-        if (src[grp] < 0) gm = 0;
+        if (!live) gm = 0;
         const double d = snap(group_zdist(t, ga, gmua, gia, gb, gmub, gib, gm, glim));
         // hand each result back to its proposing lane
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < kPerRound; ++g) {
             const double dg = __shfl(d, g * kGroup, kWave);
             if (g < cnt && lane == src[g]) on_result(dg);
         }

@@ -186,6 +186,12 @@ static int calibrate(const std::vector<std::vector<std::vector<double>>> &sets,
     std::vector<std::vector<W>> spec(sets.size());
     for (size_t s = 0; s < sets.size(); ++s) {
         const int m = ms[s];
+        // twiddles cos, sin (2 pi j / m), j < m
+        std::vector<double> tc(m), ts(m);
+        for (int j = 0; j < m; ++j) {
+            tc[j] = std::cos(6.283185307179586 * (double)j / m);
+            ts[j] = std::sin(6.283185307179586 * (double)j / m);
+        }
         for (const auto &w : sets[s]) {
             double mu = 0.0;
             for (double x : w) mu += x;
@@ -200,11 +206,13 @@ static int calibrate(const std::vector<std::vector<std::vector<double>>> &sets,
             const int kp = kprime_of(kMaxK, m);
             for (int k = 1; k <= kp; ++k) {
                 double re = 0.0, im = 0.0;
+                int j = 0;                       // (k r) mod m
                 for (int r = 0; r < m; ++r) {
                     const double z = (w[r] - mu) / sg;
-                    const double ang = 6.283185307179586 * (double)((int64_t)k * r % m) / m;
-                    re += z * std::cos(ang);
-                    im -= z * std::sin(ang);
+                    re += z * tc[j];
+                    im -= z * ts[j];
+                    j += k;
+                    if (j >= m) j -= m;
                 }
                 f.re[k] = re;
                 f.im[k] = im;
@@ -698,6 +706,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     // calibration samples
     std::vector<int> cal_m;
     std::vector<std::vector<int64_t>> cal_st;
+    std::vector<int64_t> cal_all(3 * 256, 0);   // lives until the sync below
     if (o.K == 0) {
         int idx[3] = {0, (p.L - 1) / 2, p.L - 1};
         for (int a = 0; a < 3; ++a) {
@@ -705,15 +714,15 @@ static int run_pipeline(Run &R, Arena &ar) {
             cal_m.push_back(p.ms[idx[a]]);
             cal_st.push_back(sample_starts(p.len[idx[a]].W));
         }
-        for (size_t a = 0; a < cal_m.size(); ++a) {
-            std::vector<int64_t> st = cal_st[a];
-            HIPCHK(hipMemcpyAsync(b.cal_starts, st.data(), st.size() * sizeof(int64_t),
-                                  hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_gather_windows, dim3((unsigned)st.size()), dim3(256), 0, s, R.t,
-                               (const int64_t *)b.cal_starts, (int)st.size(), cal_m[a],
+        for (size_t a = 0; a < cal_m.size(); ++a)
+            for (size_t w = 0; w < cal_st[a].size(); ++w) cal_all[a * 256 + w] = cal_st[a][w];
+        HIPCHK(hipMemcpyAsync(b.cal_starts, cal_all.data(), cal_all.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+        for (size_t a = 0; a < cal_m.size(); ++a)
+            hipLaunchKernelGGL(k_gather_windows, dim3((unsigned)cal_st[a].size()), dim3(256), 0, s,
+                               R.t, (const int64_t *)b.cal_starts + a * 256,
+                               (int)cal_st[a].size(), cal_m[a],
                                b.cal_win + (int64_t)a * 256 * p.max_m);
-            HIPCHK(hipStreamSynchronize(s));
-        }
     }
     HIPCHK(hipStreamSynchronize(s));
     if (bad) return fail(PMP_EINVAL, "series contains a non-finite sample");
