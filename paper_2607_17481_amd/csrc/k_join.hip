@@ -105,22 +105,23 @@ __device__ __forceinline__ void load_g(const uint4 *__restrict__ op, double g[2 
 
 // ------------------------------------------------- principal directions
 
-// Mean and second moments of G over an even sample of each length's
-// windows: out[l] = {count, sum[32], sum of products [32 x 32] (upper)}.
-__global__ __launch_bounds__(kBlock) void k_join_cov(Req q, const uint4 *__restrict__ jop,
-                                                     double *__restrict__ out) {
+// Mean and second moments of the FP32 feature copies over an even sample of
+// each length's windows: out[l] = {count, sum[32], sum of products [32 x 32]
+// (upper)}.
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_join_cov(Req q, double *__restrict__ out) {
     __shared__ float rows[64][2 * kMaxK + 1];
     const int l = blockIdx.x;
     const LenInfo L = q.len[l];
     const int64_t n = L.n_index;
     const int S = (int)min<int64_t>(n, kCovSample);
     double *o = out + (int64_t)l * (1 + 32 + 32 * 32);
-    // thread -> two (a, b) pairs of the upper triangle, or a mean entry
+    // thread -> pairs (a <= b < 32) of the upper triangle, or a sum entry
     double acc[5] = {0, 0, 0, 0, 0};
     int pa[5], pb[5];
 #pragma unroll
     for (int x = 0; x < 5; ++x) {
-        int p = threadIdx.x + x * kBlock;           // 0 .. 1279: 528 pairs (a <= b < 32), then 32 sums
+        int p = threadIdx.x + x * kBlock;           // 0 .. 1279: 528 pairs, then 32 sums
         pa[x] = -1;
         pb[x] = -1;
         if (p < 528) {
@@ -138,13 +139,9 @@ __global__ __launch_bounds__(kBlock) void k_join_cov(Req q, const uint4 *__restr
         for (int x = threadIdx.x; x < 64 * 32; x += kBlock) {
             const int r = x / 32, c = x % 32;
             float v = 0.0f;
-            if (s0 + r < S) {
+            if (s0 + r < S && c < 2 * (kMaxK - 1)) {
                 const int64_t k = L.kbase + (int64_t)(((double)(s0 + r) + 0.5) * (double)n / (double)S);
-                const uint32_t *w = (const uint32_t *)(jop + k * 8);
-                const uint32_t h = w[c / 2], lo = w[16 + c / 2];
-                const uint32_t hb = (c & 1) ? (h & 0xFFFF0000u) : (h << 16);
-                const uint32_t lb = (c & 1) ? (lo & 0xFFFF0000u) : (lo << 16);
-                v = __uint_as_float(hb) + __uint_as_float(lb);
+                v = (float)((const FT *)q.F)[k * kRec + c];
             }
             rows[r][c] = v;
         }
@@ -166,37 +163,94 @@ __global__ __launch_bounds__(kBlock) void k_join_cov(Req q, const uint4 *__restr
     }
 }
 
+namespace {
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+}  // namespace
+
+// The kJoinDirs leading principal directions of each length's sample (power
+// iteration on the covariance, each deflated against the ones before), made
+// orthonormal in FP64; one wavefront per length, lane i holds component i.
+// Any orthonormal set keeps the threshold join exact; the leading directions
+// make its cells selective.  udir[l][v][0..31] (components 30, 31 are 0).
+__global__ __launch_bounds__(kWave) void k_pca(const double *__restrict__ cov, int L,
+                                               double *__restrict__ udir) {
+    constexpr int D = 2 * (kMaxK - 1);
+    __shared__ double C[D][D + 1];
+    __shared__ double xs[32];
+    const int l = blockIdx.x;
+    if (l >= L) return;
+    const int i = threadIdx.x;
+    const double *c = cov + (int64_t)l * (1 + 32 + 32 * 32);
+    const double S = c[0];
+    if (i < D)
+        for (int b = 0; b < D; ++b) {
+            const int lo = min(i, b), hi = max(i, b);
+            C[i][b] = S >= 2.0 ? c[33 + lo * 32 + hi] / S - (c[1 + i] / S) * (c[1 + b] / S) : 0.0;
+        }
+    __syncthreads();
+    double u[kJoinDirs];
+    for (int v = 0; v < kJoinDirs; ++v) {
+        double x = i < D ? 1.0 + 0.37 * ((i * (v + 3)) % 7) - 0.5 * (i % (v + 2)) : 0.0;
+        // deflate against the directions before, then normalize
+        for (int w = 0; w < v; ++w) x -= wave_sum_d(x * u[w]) * u[w];
+        double nn = sqrt(wave_sum_d(x * x));
+        if (nn > 1e-300) {
+            x /= nn;
+            for (int it = 0; it < 64; ++it) {
+                __syncthreads();
+                if (i < 32) xs[i] = x;
+                __syncthreads();
+                double y = 0.0;
+                if (i < D)
+                    for (int j = 0; j < D; ++j) y = fma(C[i][j], xs[j], y);
+                for (int w = 0; w < v; ++w) y -= wave_sum_d(y * u[w]) * u[w];
+                const double ny = sqrt(wave_sum_d(y * y));
+                if (!(ny > 1e-300)) break;
+                x = y / ny;
+            }
+        }
+        // exact orthonormality against the ones before (twice, for
+        // rounding); a degenerate vector falls back to a unit vector
+        for (int e = 0;; ++e) {
+            for (int r = 0; r < 2; ++r)
+                for (int w = 0; w < v; ++w) x -= wave_sum_d(x * u[w]) * u[w];
+            const double nx = sqrt(wave_sum_d(x * x));
+            if (nx > 1e-300) { x /= nx; break; }
+            x = i == e ? 1.0 : 0.0;
+        }
+        for (int r = 0; r < 2; ++r) {
+            for (int w = 0; w < v; ++w) x -= wave_sum_d(x * u[w]) * u[w];
+            x /= sqrt(wave_sum_d(x * x));
+        }
+        u[v] = i < D ? x : 0.0;
+        if (i < 32) udir[((int64_t)l * kJoinDirs + v) * 32 + i] = u[v];
+    }
+}
+
 // ------------------------------------------------------------ grid keys
 
-// Sort key (length, cell1, cell2) and value k of every indexed window, its
-// three principal coordinates, and its query flag (cell not yet at 0) for
-// this round.  With cb2 = 0 the grid
+// Sort key (length, cell1, cell2) and value k of every indexed window (from
+// its principal coordinates, computed by k_keys), and its query flag (cell
+// not yet at 0) for this round.  With cb2 = 0 the grid
 // has one coordinate only, in finer cells (a band), for radii below the
 // resolution of the two-coordinate grid.
-template <typename FT>
 __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__restrict__ gl,
                                                       int64_t N, int cb1, int cb2,
                                                       uint32_t *__restrict__ gkey,
                                                       uint32_t *__restrict__ gval,
                                                       uint8_t *__restrict__ qf,
-                                                      float4 *__restrict__ gp) {
+                                                      const float4 *__restrict__ gp) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
     const int64_t k_first = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
     const int l = find_len_k_wave(q.len, q.L, k_first, k);
     const GridLen &G = gl[l];
-    // coordinates of the FP32 copy f of the stored record: a coordinate of a
-    // pair moves by at most |f_i - f_j| <= |F_i - F_j| + e_i + e_j + u32 (|F~_i| + |F~_j|)
-    const FT *rec = (const FT *)q.F + k * kRec;
-    double p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll
-    for (int c = 0; c < 2 * (kMaxK - 1); ++c) {
-        const double x = (double)(float)rec[c];
-        p1 = fma(G.u[0][c], x, p1);
-        p2 = fma(G.u[1][c], x, p2);
-        p3 = fma(G.u[2][c], x, p3);
-    }
-    gp[k] = make_float4((float)p1, (float)p2, (float)p3, 0.0f);
+    const float4 c = gp[k];
+    const double p1 = c.x, p2 = c.y;
     auto cell = [&](double p, int bits) -> uint32_t {
         const uint32_t top = (1u << bits) - 1u;
         const double x = (p - G.qlo) * G.hinv;
@@ -434,20 +488,20 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kB
 
 size_t join_cov_doubles(int L) { return (size_t)L * (1 + 32 + 32 * 32); }
 
-void launch_join_cov(const Req &q, const uint4 *jop, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_join_cov, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, jop, out);
+void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s) {
+    if (precision == 0)
+        hipLaunchKernelGGL(k_join_cov<double>, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, cov);
+    else
+        hipLaunchKernelGGL(k_join_cov<float>, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, cov);
+    hipLaunchKernelGGL(k_pca, dim3((unsigned)q.L), dim3(kWave), 0, s, cov, q.L, udir);
 }
 
-void launch_grid_keys(int precision, const Req &q, const GridLen *gl, int64_t N, int cb1,
-                      int cb2, uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
+void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2,
+                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, const float4 *gp,
                       hipStream_t s) {
     if (N <= 0) return;
-    if (precision == 0)
-        hipLaunchKernelGGL(k_grid_keys<double>, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1,
-                           cb2, gkey, gval, qf, gp);
-    else
-        hipLaunchKernelGGL(k_grid_keys<float>, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1,
-                           cb2, gkey, gval, qf, gp);
+    hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1, cb2, gkey,
+                       gval, qf, gp);
 }
 
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,

@@ -578,6 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *_
 namespace {
 struct KeysSmem {
     float g[kMaxBits * kGLd];                 // SimHash projections of the length
+    double u[kJoinDirs][32];                  // the join's principal directions
 };
 
 }  // namespace
@@ -598,6 +599,9 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
     const int tid = threadIdx.x;
     for (int x = tid; x < q.B * kGLd; x += kBlock)
         sm.g[x] = x % kGLd < kFD ? gproj[((int64_t)l * q.B + x / kGLd) * kFD + x % kGLd] : 0.0f;
+    if (q.udir)
+        for (int x = tid; x < kJoinDirs * 32; x += kBlock)
+            sm.u[x / 32][x % 32] = q.udir[(int64_t)l * kJoinDirs * 32 + x];
     __syncthreads();
     const int64_t j = ((int64_t)blockIdx.x - L.blk_base) * kBlock + tid;
     if (j >= L.n_index) return;
@@ -696,6 +700,17 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
     for (int part = 0; part < 4; ++part) {
         jo[part] = make_uint4(hw[4 * part], hw[4 * part + 1], hw[4 * part + 2], hw[4 * part + 3]);
         jo[4 + part] = make_uint4(lw[4 * part], lw[4 * part + 1], lw[4 * part + 2], lw[4 * part + 3]);
+    }
+    // principal coordinates of the FP32 copy (FP64 dots), for the join's grid
+    if (q.udir) {
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kFD; ++c) {
+            p0 = fma(sm.u[0][c], (double)f[c], p0);
+            p1 = fma(sm.u[1][c], (double)f[c], p1);
+            p2 = fma(sm.u[2][c], (double)f[c], p2);
+        }
+        q.gp[kk] = make_float4((float)p0, (float)p1, (float)p2, 0.0f);
     }
     const double ep = ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
     q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),

@@ -64,6 +64,8 @@ struct Req {
     uint64_t *keyw;        // [N] key word: signature | probe order << 24
     uint4   *jop;          // [N][8] join operands: 32 bf16 hi, then 32 bf16 lo (G = hi + lo)
     float4  *jmeta;        // [N] |G|^2, e' >= |G - F|, bound on |G|, 0
+    float4  *gp;           // [N] principal coordinates of the FP32 feature copy, 0
+    const double *udir;    // [L][kJoinDirs][32] principal directions (null: none)
     // bucket order (slots)
     uint32_t *skey;        // [N] sort keys
     uint32_t *sval;        // [N] sort values (k)
@@ -140,7 +142,6 @@ struct GridLen {
     double R2;            // squared radius on the join vectors G (+inf: every pair)
     double eps_c;         // MFMA dot-product error per unit |G_q| (times the largest |G_c|)
     double nmax2;         // square of the largest |G|
-    double u[kJoinDirs][2 * (kMaxK - 1)];   // principal directions (orthonormal)
     float sqrt2m;         // sqrt(2/m) (1 + 1e-7)
     float rp;             // bound on any coordinate difference of a pair within R_f
 };
@@ -364,9 +365,10 @@ void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t n
                         uint32_t cap, uint32_t *eq, hipStream_t s);
 // (k_join.hip)
 size_t join_cov_doubles(int L);
-void launch_join_cov(const Req &q, const uint4 *jop, double *out, hipStream_t s);
-void launch_grid_keys(int precision, const Req &q, const GridLen *gl, int64_t N, int cb1,
-                      int cb2, uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
+// principal directions: covariance of a sample, then power iteration (GPU)
+void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s);
+void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2,
+                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, const float4 *gp,
                       hipStream_t s);
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,

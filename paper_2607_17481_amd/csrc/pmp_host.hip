@@ -107,65 +107,6 @@ static double gauss(uint64_t seed, int m, int l, int c) {
 
 constexpr int kFD = 2 * (kMaxK - 1);   // 30 feature reals
 
-// The kJoinDirs leading principal directions of one length's sampled join
-// vectors G (power iteration on their covariance, each deflated against the
-// ones before), made orthonormal in FP64.  Any orthonormal set keeps the
-// threshold join exact; the leading directions make its cells selective.
-// c: {count, sum[32], sum of products [32][32] (upper triangle)}.
-static void principal_dirs(const double *c, double u[kJoinDirs][kFD]) {
-    const double S = c[0];
-    auto normalize = [](double *x) {
-        double n = 0.0;
-        for (int i = 0; i < kFD; ++i) n += x[i] * x[i];
-        n = std::sqrt(n);
-        if (!(n > 1e-300)) return false;
-        for (int i = 0; i < kFD; ++i) x[i] /= n;
-        return true;
-    };
-    auto orth = [](double *x, const double *w) {
-        double d = 0.0;
-        for (int i = 0; i < kFD; ++i) d += x[i] * w[i];
-        for (int i = 0; i < kFD; ++i) x[i] -= d * w[i];
-    };
-    double C[kFD][kFD];
-    for (int a = 0; a < kFD; ++a)
-        for (int b = a; b < kFD; ++b) {
-            const double v = S >= 2.0 ? c[33 + a * 32 + b] / S - (c[1 + a] / S) * (c[1 + b] / S) : 0.0;
-            C[a][b] = v;
-            C[b][a] = v;
-        }
-    for (int v = 0; v < kJoinDirs; ++v) {
-        double x[kFD], y[kFD];
-        for (int i = 0; i < kFD; ++i) x[i] = 1.0 + 0.37 * ((i * (v + 3)) % 7) - 0.5 * (i % (v + 2));
-        for (int w = 0; w < v; ++w) orth(x, u[w]);
-        if (normalize(x)) {
-            for (int it = 0; it < 64; ++it) {
-                for (int i = 0; i < kFD; ++i) {
-                    double a = 0.0;
-                    for (int j = 0; j < kFD; ++j) a += C[i][j] * x[j];
-                    y[i] = a;
-                }
-                for (int w = 0; w < v; ++w) orth(y, u[w]);
-                if (!normalize(y)) break;
-                for (int i = 0; i < kFD; ++i) x[i] = y[i];
-            }
-        }
-        // exact orthonormality against the ones before (twice, for rounding);
-        // a degenerate start falls back to a unit vector
-        for (int e = 0;; ++e) {
-            for (int r = 0; r < 2; ++r)
-                for (int w = 0; w < v; ++w) orth(x, u[w]);
-            if (normalize(x)) break;
-            for (int i = 0; i < kFD; ++i) x[i] = i == e ? 1.0 : 0.0;
-        }
-        for (int r = 0; r < 2; ++r) {
-            for (int w = 0; w < v; ++w) orth(x, u[w]);
-            normalize(x);
-        }
-        for (int i = 0; i < kFD; ++i) u[v][i] = x[i];
-    }
-}
-
 static int kprime_of(int K, int m) {
     int half = (m + 1) / 2 - 1;
     int kp = std::min(K - 1, half);
@@ -375,7 +316,7 @@ struct Bufs {
     int *bad;
     unsigned long long *counters;
     float *emax, *gproj;
-    double *cov;
+    double *cov, *udir;
     GridLen *gl;
     int64_t *bbase;            // MFMA sketch basis: offsets per length, then hi / lo tables
     uint16_t *bh, *bl;
@@ -415,6 +356,7 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.emax = take<float>(a, p.L);
     b.gproj = take<float>(a, (int64_t)p.L * kMaxBits * kFD);
     b.cov = take<double>(a, (int64_t)join_cov_doubles(p.L));
+    b.udir = take<double>(a, (int64_t)p.L * kJoinDirs * 32);
     {
         std::vector<int64_t> base;
         const int64_t ne = basis_elems(p.len.data(), p.L, base);
@@ -783,6 +725,8 @@ static int run_pipeline(Run &R, Arena &ar) {
     q.keyw = b.keyw;
     q.jop = b.jop;
     q.jmeta = b.jmeta;
+    q.gp = b.gp;
+    q.udir = o.certify ? b.udir : nullptr;
     q.skey = b.skey;
     q.sval = b.sval;
     q.perm = b.sval;
@@ -807,6 +751,8 @@ static int run_pipeline(Run &R, Arena &ar) {
         launch_sketch_mfma(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, b.bbase, b.bh, b.bl,
                            s);
     }
+    // the join's principal directions (GPU), used by the keys kernel
+    if (o.certify && N > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
     launch_keys(o.precision, q, p.nkblocks, s);
     tm.mark(2, s);
     radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
@@ -836,17 +782,12 @@ static int run_pipeline(Run &R, Arena &ar) {
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
     if (o.certify && N > 0) {
-        // principal directions of each length (once)
-        std::vector<double> cov(join_cov_doubles(p.L));
-        launch_join_cov(q, b.jop, b.cov, s);
-        HIPCHK(hipMemcpyAsync(cov.data(), b.cov, cov.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         std::vector<float> emax(p.L);
         HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         std::vector<GridLen> gl(p.L);
         int64_t ntiles = 0;
         for (int l = 0; l < p.L; ++l) {
-            principal_dirs(cov.data() + (size_t)l * (1 + 32 + 32 * 32), gl[l].u);
             gl[l].tile_base = ntiles;
             ntiles += (p.len[l].n_index + kJoinTile - 1) / kJoinTile;
         }
@@ -900,7 +841,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                 G.sqrt2m = (float)std::sqrt(2.0 / m) * (1.0f + 1e-7f);
             }
             HIPCHK(hipMemcpyAsync(b.gl, gl.data(), p.L * sizeof(GridLen), hipMemcpyHostToDevice, s));
-            launch_grid_keys(o.precision, q, b.gl, N, cb1, cb2, b.jk, b.jv, b.qf, b.gp, s);
+            launch_grid_keys(q, b.gl, N, cb1, cb2, b.jk, b.jv, b.qf, b.gp, s);
             radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + cb1 + cb2, b.sort_tmp, s);
             launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntiles,
                               cb1, cb2, Teff, s);
