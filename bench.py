@@ -101,13 +101,17 @@ def algorithmic_bytes(n, lengths, st, fs):
     return {"k_sketch": float(sketch), "k_probe": float(probe), "k_join": float(join)}
 
 
-KERNEL_SOURCES = {"k_sketch": "k_sketch.hip", "k_probe": "k_probe.hip", "k_join": "k_certify.hip"}
+# the source files of each timed phase's kernels: the sketch phase is the
+# sketch, the join's principal directions and the keys; the join phase's
+# dominant kernels are the grid keys and the tile join
+KERNEL_SOURCES = {"k_sketch": ("k_sketch.hip", "k_join.hip"), "k_probe": ("k_probe.hip",),
+                  "k_join": ("k_join.hip", "k_certify.hip")}
 
 
 def source_digest(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCES[kernel], "pmp_dev.h"):
+    for f in KERNEL_SOURCES[kernel] + ("pmp_dev.h",):
         with open(os.path.join(ROOT, "paper_2607_17481_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -265,9 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
 
 // ------------------------------------------------------------ the tiles
 
-// One wavefront per tile of 32 consecutive sorted windows of one length.
+// One wavefront per tile of 32 consecutive sorted windows of one length, and
+// one wavefront per block: tile costs vary widely, and a single-wave block
+// frees its slot (and its LDS queue) as soon as its own tile is done.
+constexpr int kJoinWaves = 1;
 template <typename FT>
-__global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__restrict__ gl,
+__global__ __launch_bounds__(kJoinWaves * kWave) void k_join_tiles(Req q, const GridLen *__restrict__ gl,
                                                        const uint32_t *__restrict__ gkey,
                                                        const uint32_t *__restrict__ gval,
                                                        const uint8_t *__restrict__ qf,
@@ -276,11 +279,11 @@ __global__ __launch_bounds__(kBlock) void k_join_tiles(Req q, const GridLen *__r
                                                        const float4 *__restrict__ gp,
                                                        int64_t ntiles, int cb1, int cb2,
                                                        double T) {
-    __shared__ uint2 queue[kBlock / kWave][kQueueCap];
-    __shared__ float4 rowt[kBlock / kWave][kJT];          // query coordinates and filter term
+    __shared__ uint2 queue[kJoinWaves][kQueueCap];
+    __shared__ float4 rowt[kJoinWaves][kJT];          // query coordinates and filter term
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int64_t tile = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
+    const int64_t tile = (int64_t)blockIdx.x * kJoinWaves + wv;
     if (tile >= ntiles) return;
     int l;
     {
@@ -509,13 +512,13 @@ void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uin
                        const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
                        double T, hipStream_t s) {
     if (ntiles <= 0) return;
-    const unsigned nb = (unsigned)((ntiles + kBlock / kWave - 1) / (kBlock / kWave));
+    const unsigned nb = (unsigned)((ntiles + kJoinWaves - 1) / kJoinWaves);
     if (precision == 0)
-        hipLaunchKernelGGL(k_join_tiles<double>, dim3(nb), dim3(kBlock), 0, s, q, gl, gkey, gval,
-                           qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
+        hipLaunchKernelGGL(k_join_tiles<double>, dim3(nb), dim3(kJoinWaves * kWave), 0, s, q, gl,
+                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
     else
-        hipLaunchKernelGGL(k_join_tiles<float>, dim3(nb), dim3(kBlock), 0, s, q, gl, gkey, gval,
-                           qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
+        hipLaunchKernelGGL(k_join_tiles<float>, dim3(nb), dim3(kJoinWaves * kWave), 0, s, q, gl,
+                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
 }
 
 }  // namespace pmp

@@ -31,12 +31,15 @@
 namespace pmp {
 
 // Queries are taken in (length, start) order (indexed position k), so that
-// neighbouring windows, which tend to cost alike, share a wavefront.
+// neighbouring windows, which tend to cost alike, share a wavefront.  A block
+// is one wavefront: wavefront times vary over two orders of magnitude, and a
+// single-wave block lets a compute unit start new work as soon as any one
+// wavefront ends, not when a slot for four is free.
 template <typename FT>
-__global__ __launch_bounds__(kBlock) void k_probe(Req q, const uint32_t *__restrict__ bstart,
+__global__ __launch_bounds__(kWave) void k_probe(Req q, const uint32_t *__restrict__ bstart,
                                                   int64_t N) {
-    const int64_t k_first = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k_first = (int64_t)blockIdx.x * kWave;
+    const int64_t k = k_first + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
     int64_t s = 0;
 
@@ -179,10 +182,11 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kB
 
 void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, hipStream_t s) {
     if (N <= 0) return;
+    const dim3 grid((unsigned)((N + kWave - 1) / kWave));
     if (precision == 0)
-        hipLaunchKernelGGL(k_probe<double>, dim3(nblk(N)), dim3(kBlock), 0, s, q, bstart, N);
+        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), 0, s, q, bstart, N);
     else
-        hipLaunchKernelGGL(k_probe<float>, dim3(nblk(N)), dim3(kBlock), 0, s, q, bstart, N);
+        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), 0, s, q, bstart, N);
 }
 
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,

@@ -162,24 +162,25 @@ struct RowReq {
 // of a group are contiguous.  All 64 lanes of the wavefront must call it.
 constexpr int kGroup = 8;                 // lanes per exact distance
 constexpr int kPerRound = kWave / kGroup; // distances per wavefront round
+constexpr int kZBatch = 8;                // terms per lane loaded together
 
 __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
                                               double ia, int64_t b, double mub, double ib, int m,
                                               double lim2 = INFINITY) {
 #pragma clang fp contract(off)
     double acc = 0.0;
-    // four terms per lane are loaded before they are summed (in order), so
-    // that a short window costs one memory latency
-    for (int r0 = lane_id() & (kGroup - 1); r0 < m; r0 += 4 * kGroup) {
-        double xa[4], xb[4];
+    // kZBatch terms per lane are loaded before they are summed (in order), so
+    // that a window of up to kZBatch * kGroup samples costs one memory latency
+    for (int r0 = lane_id() & (kGroup - 1); r0 < m; r0 += kZBatch * kGroup) {
+        double xa[kZBatch], xb[kZBatch];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kZBatch; ++u) {
             const int r = r0 + u * kGroup;
             xa[u] = r < m ? t[a + r] : 0.0;
             xb[u] = r < m ? t[b + r] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kZBatch; ++u) {
             if (r0 + u * kGroup < m) {
                 const double za = (xa[u] - mua) * ia;
                 const double zb = (xb[u] - mub) * ib;
@@ -191,7 +192,7 @@ __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int6
         // rounding is monotone), so once their total reaches lim2 the
         // finished sum would too; the group decides together (all its lanes
         // compute the same total)
-        if (lim2 != INFINITY && (r0 | (kGroup - 1)) + 1 + 3 * kGroup < m) {
+        if (lim2 != INFINITY && (r0 | (kGroup - 1)) + 1 + (kZBatch - 1) * kGroup < m) {
             double sp = acc;
 #pragma unroll
             for (int off = 1; off < kGroup; off <<= 1) sp += __shfl_xor(sp, off, kGroup);

@@ -758,10 +758,10 @@ static int run_pipeline(Run &R, Arena &ar) {
     radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
     launch_bucket_bounds(q, N, p.nbuckets, b.bstart, s);
     launch_slot_maps(q, N, s);
+    launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
     tm.mark(3, s);
     tm.mark(4, s);
     launch_probe(o.precision, q, b.bstart, N, s);
-    launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
     tm.mark(5, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
