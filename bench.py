@@ -210,6 +210,31 @@ def serving_bench(cfg):
     return out
 
 
+SERVING_SWEEP = {"requests": 120, "n_lo": 10_000, "n_hi": 2_000_000, "slots": 4,
+                 "hbm_budget_gb": 192, "loads": (0.5, 0.8, 1.0)}
+
+
+def serving_sweep(cfg):
+    """The serving measurement over offered loads: requests with series
+    lengths log-uniform up to 2e6, FP64 form, open loop at each fraction of
+    the closed-loop capacity.  Progress goes to stderr, one line per run."""
+    reqs = synth.serving_requests(cfg["requests"], 1.0, cfg["n_lo"], cfg["n_hi"])
+    series = [r.series() for r in reqs]
+    budget = cfg["hbm_budget_gb"] << 30
+    cap = serving_run(0, reqs, series, 0.0, cfg["slots"], budget)["req_per_s"]
+    print(f"capacity {cap:.3f} req/s", file=sys.stderr, flush=True)
+    out = {"metric": "serving latency over offered load", "form": "fp64",
+           "requests": len(reqs), "n_range": [cfg["n_lo"], cfg["n_hi"]], "slots": cfg["slots"],
+           "hbm_budget_gb": cfg["hbm_budget_gb"], "capacity_req_per_s": cap, "loads": {}}
+    for f in cfg["loads"]:
+        r = serving_run(0, reqs, series, f * cap, cfg["slots"], budget)
+        r["offered_req_per_s"] = f * cap
+        out["loads"][str(f)] = r
+        print(f"load {f}: p50 {r['p50_ms']:.0f} ms p99 {r['p99_ms']:.0f} ms", file=sys.stderr,
+              flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +247,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the copy kernel that scales the HBM counters")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="only run the serving measurement at 0.5 / 0.8 / 1.0 of capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the workload fits one MI355X); "
@@ -229,6 +256,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.serving_sweep:
+        serving_sweep(SERVING_SWEEP)
         return
 
     import torch

@@ -125,7 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_select_emit(const uint64_t *__restri
 // Pass 1 (find_min = 1): out_min[c] = min over valid j of the snapped
 // distance.  Pass 2: out_arg[c] = smallest valid j whose snapped distance
 // equals req[c].target.  Constant windows are not indexed and never scanned.
-// Each group of kGroup lanes takes every (groups)-th window of the length.
+// Each lane takes every (threads)-th window of the length and evaluates the
+// canonical distance on its own (lane_zdist): neighbouring lanes read
+// neighbouring windows, and the row's own window is shared by all.
 __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict__ rr, int find_min,
                                                  unsigned long long *__restrict__ out_min,
                                                  unsigned long long *__restrict__ out_arg) {
@@ -134,29 +136,19 @@ __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict
     const int m = L.m;
     const int64_t i = (int64_t)q.cell[R.k] - L.cell_base;
     const double mui = q.mu[R.k], isi = q.isig[R.k];
-    constexpr int kGroupsPerBlock = kBlock / kGroup;
-    const int64_t g0 = (int64_t)blockIdx.x * kGroupsPerBlock + threadIdx.x / kGroup;
-    const int64_t ng = (int64_t)gridDim.x * kGroupsPerBlock;
-    // every group runs the same number of iterations (uniform control flow)
-    const int64_t iters = (L.n_index + ng - 1) / ng;
+    const int64_t nt = (int64_t)gridDim.x * kBlock;
     unsigned long long best = find_min ? (unsigned long long)kInfBits : ~0ull;
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t x = g0 + it * ng;
-        bool ok = x < L.n_index;
-        const int64_t kc = L.kbase + (ok ? x : 0);
+    for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < L.n_index; x += nt) {
+        const int64_t kc = L.kbase + x;
         const int64_t j = (int64_t)q.cell[kc] - L.cell_base;
         const int64_t gap = j > i ? j - i : i - j;
-        ok = ok && gap >= q.excl;
-        const double dd = snap(group_zdist(q.t, i, mui, isi, ok ? j : i, ok ? q.mu[kc] : 0.0,
-                                           ok ? q.isig[kc] : 0.0, ok ? m : 0));
-        if (ok) {
-            const unsigned long long b = (unsigned long long)dbits(dd);
-            if (find_min) best = b < best ? b : best;
-            else if (b == R.target && (unsigned long long)j < best) best = (unsigned long long)j;
-        }
+        if (gap < q.excl) continue;
+        const double dd = snap(lane_zdist(q.t, i, mui, isi, j, q.mu[kc], q.isig[kc], m));
+        const unsigned long long b = (unsigned long long)dbits(dd);
+        if (find_min) best = b < best ? b : best;
+        else if (b == R.target && (unsigned long long)j < best) best = (unsigned long long)j;
     }
-    // all lanes of a group hold the same value; reduce across the wave
-    for (int off = kGroup; off < kWave; off <<= 1) {
+    for (int off = 1; off < kWave; off <<= 1) {
         const unsigned long long o = __shfl_xor(best, off, kWave);
         best = o < best ? o : best;
     }
@@ -216,7 +208,7 @@ void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t n
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s) {
     if (nrows <= 0) return;
-    hipLaunchKernelGGL(k_rows, dim3(gridcap(maxN / 4, 1024), (unsigned)nrows), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(k_rows, dim3(gridcap(maxN, 1024), (unsigned)nrows), dim3(kBlock), 0, s,
                        q, rr, find_min, out_min, out_arg);
 }
 

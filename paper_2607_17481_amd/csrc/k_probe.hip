@@ -15,8 +15,11 @@
 // below max(P[q], P[c]) -- the two cells the pair can lower (Sec. 3.4, the
 // definition of S_stream).  Each exact distance lowers both cells through a
 // 64-bit atomic min on the FP64 bit pattern (non-negative doubles order like
-// their bit patterns), which is order independent, so the profile does not
-// depend on the schedule (the role of the fixed merge order of Prop. 5).
+// their bit patterns), which is order independent.  Which candidates pass the
+// prune depends on how far the cells have been lowered when they are
+// inspected, so the upper profile may differ slightly between runs; the exact
+// top-k built on it by the certificate does not (the role of the fixed merge
+// order of Prop. 5).
 //
 // GPU mapping: one lane per query searches its candidates (lane-parallel
 // bound tests); the exact distances of the proposals (one per lane per round)

@@ -163,6 +163,10 @@ struct RowReq {
 constexpr int kGroup = 8;                 // lanes per exact distance
 constexpr int kPerRound = kWave / kGroup; // distances per wavefront round
 constexpr int kZBatch = 8;                // terms per lane loaded together
+constexpr int kLaneMode = 32;             // proposals from which each lane takes its own,
+constexpr int kLaneModeMaxM = 100;        // for windows up to this length: longer ones
+                                          // read better in groups (contiguous loads);
+                                          // measured crossover between 100 and 124
 
 __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
                                               double ia, int64_t b, double mub, double ib, int m,
@@ -202,6 +206,47 @@ __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int6
 #pragma unroll
     for (int off = 1; off < kGroup; off <<= 1) acc += __shfl_xor(acc, off, kGroup);
     return sqrt(acc);
+}
+
+// The same canonical distance evaluated by one lane alone, bit for bit: the
+// kGroup partial sums of group_zdist become kGroup accumulators of the lane
+// (accumulator g takes the terms r = g, g + kGroup, ... in ascending order),
+// combined in the order of group_zdist's butterfly.  Used when most lanes of a
+// wavefront have a pair of their own, where it avoids the group's shuffles.
+static_assert(kGroup == 8, "lane_zdist combines eight partial sums");
+__device__ __forceinline__ double butterfly8(const double *p) {
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+__device__ __forceinline__ double lane_zdist(const double *__restrict__ t, int64_t a, double mua,
+                                             double ia, int64_t b, double mub, double ib, int m,
+                                             double lim2 = INFINITY) {
+#pragma clang fp contract(off)
+    double acc[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) acc[g] = 0.0;
+    for (int r0 = 0; r0 < m; r0 += kGroup) {
+        double xa[kGroup], xb[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            xa[g] = r0 + g < m ? t[a + r0 + g] : 0.0;
+            xb[g] = r0 + g < m ? t[b + r0 + g] : 0.0;
+        }
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            if (r0 + g < m) {
+                const double za = (xa[g] - mua) * ia;
+                const double zb = (xb[g] - mub) * ib;
+                const double e = za - zb;
+                acc[g] = fma(e, e, acc[g]);
+            }
+        }
+        // early exit as in group_zdist (any partial total is a lower bound
+        // of the finished sum), tested every kZBatch terms per accumulator
+        if (lim2 != INFINITY && ((r0 / kGroup) % kZBatch) == kZBatch - 1 && r0 + kGroup < m &&
+            butterfly8(acc) >= lim2)
+            return INFINITY;
+    }
+    return sqrt(butterfly8(acc));
 }
 
 // Squared bound for group_zdist's early exit: a sum that reaches it has a
@@ -276,15 +321,25 @@ __device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__r
 // Verification of the proposals of a wavefront.  Every lane whose bit is set
 // in `mask` has a proposal (a, b: window starts; mua, ia, mub, ib: moments;
 // m; lim2: the squared distance at or above which the result is of no use,
-// see exit_bound).  The proposals are taken kPerRound at a time, one per
-// group of kGroup lanes; `on_result(d)` runs on the proposing lane with its snapped distance
-// (+inf when the sum stopped early).
+// see exit_bound).  With at least kLaneMode proposals of windows up to
+// kLaneModeMaxM samples (the length of the first proposal decides for the
+// wavefront) every proposing lane evaluates its own (lane_zdist); otherwise
+// they are taken kPerRound at a time,
+// one per group of kGroup lanes (group_zdist).  Both give the same bits.
+// `on_result(d)` runs on the proposing lane with its snapped distance (+inf
+// when the sum stopped early).
 template <typename F>
 __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__restrict__ t,
                                                  int64_t a, double mua, double ia, int64_t b,
                                                  double mub, double ib, int m, F &&on_result,
                                                  double lim2 = INFINITY) {
     const int lane = lane_id();
+    if (__popcll(mask) >= kLaneMode &&
+        __shfl(m, __ffsll((unsigned long long)mask) - 1, kWave) <= kLaneModeMaxM) {
+        // most lanes propose short windows: each evaluates its own pair
+        if ((mask >> lane) & 1ull) on_result(snap(lane_zdist(t, a, mua, ia, b, mub, ib, m, lim2)));
+        return;
+    }
     const int grp = lane / kGroup;
     while (mask) {
         // the next kPerRound proposing lanes, in lane order

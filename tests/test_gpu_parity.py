@@ -112,6 +112,13 @@ def test_random_walk_all_lengths_profile_certified(gpu, ws, oracle, prec):
     assert exact.sum() > 0
     np.testing.assert_allclose(P_fin[exact], P_or[exact], rtol=1e-9)
     assert np.all(P_fin[fin] >= P_or[fin] * (1 - 1e-9))
+    # every kernel evaluates the one canonical distance (one lane or a group
+    # of eight, the same bits): where the pass already holds a cell's exact
+    # value, it is bit-identical to the certified one
+    same = exact.copy()
+    same[exact] = np.abs(P_pass[exact] - P_fin[exact]) <= 1e-9 * P_fin[exact]
+    assert same.sum() > 0.5 * exact.sum()
+    assert np.array_equal(P_pass[same], P_fin[same])
 
 
 # ------------------------------------------------------- stages a1 .. a6
