@@ -265,12 +265,77 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
 
 // ------------------------------------------------------------ the tiles
 
+// The exact stage of a tile's queued pairs (whole wavefront): each pair that
+// is no self pair, not taken by an earlier query's tile and outside the
+// exclusion zone gets the certified Parseval bound from the stored records,
+// and if the bound leaves it able to lower one of its cells below T, the
+// canonical FP64 distance.  Returns (pairs inspected, distances computed) of
+// this lane.
+template <typename FT>
+__device__ __forceinline__ uint2 join_exact(const double *__restrict__ t,
+                                         const uint32_t *__restrict__ cell, uint64_t *P,
+                                         const void *F, const double *__restrict__ mu,
+                                         const double *__restrict__ isig,
+                                         const uint32_t *__restrict__ gval,
+                                         const uint8_t *__restrict__ qf, const uint2 *queue,
+                                         int qn, int64_t pbeg, int64_t cell_base, int excl, int m,
+                                         float sqrt2m, double T) {
+    const int lane = lane_id();
+    uint32_t n_kept = 0, n_ver = 0;
+    for (int base = 0; base < qn; base += kWave) {
+        const int e = base + lane;
+        bool has = false;
+        uint32_t ki = 0, kc = 0;
+        int64_t si = 0, sc = 0;
+        double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0, lim = INFINITY;
+        if (e < qn) {
+            const uint2 pr = queue[e];
+            const int64_t pi_ = pbeg + pr.x, pc_ = pbeg + pr.y;
+            ki = gval[pi_];
+            kc = gval[pc_];
+            if (pc_ != pi_ && !(qf[kc] && pc_ < pi_)) {
+                si = (int64_t)cell[ki] - cell_base;
+                sc = (int64_t)cell[kc] - cell_base;
+                const int64_t gap = si > sc ? si - sc : sc - si;
+                if (gap >= excl) {
+                    Pi = bitsd(P[ki]);
+                    Pc = bitsd(P[kc]);
+                    const double thr = fmin(T, fmax(Pi, Pc));
+                    if (thr > 0.0) {
+                        const float lb = lb_mem<FT>((const FT *)F + (int64_t)ki * kRec,
+                                                    (const FT *)F + (int64_t)kc * kRec, sqrt2m);
+                        if ((double)lb <= T && ((double)lb < Pi || (double)lb < Pc)) {
+                            has = true;
+                            lim = exit_bound(thr);
+                            mui = mu[ki];
+                            isi = isig[ki];
+                            muc = mu[kc];
+                            isc = isig[kc];
+                        }
+                    }
+                }
+            }
+        }
+        const uint64_t mask = __ballot(has);
+        n_kept += e < qn;
+        if (mask)
+            verify_proposals<false>(mask, t, si, mui, isi, sc, muc, isc, m, [&](double dd) {
+                ++n_ver;
+                const unsigned long long db = (unsigned long long)dbits(dd);
+                if (dd < Pi) atomicMin((unsigned long long *)&P[ki], db);
+                if (dd < Pc) atomicMin((unsigned long long *)&P[kc], db);
+            }, lim);
+    }
+    return make_uint2(n_kept, n_ver);
+}
+
 // One wavefront per tile of 32 consecutive sorted windows of one length, and
 // one wavefront per block: tile costs vary widely, and a single-wave block
 // frees its slot (and its LDS queue) as soon as its own tile is done.
 constexpr int kJoinWaves = 1;
 template <typename FT>
-__global__ __launch_bounds__(kJoinWaves * kWave) void k_join_tiles(Req q, const GridLen *__restrict__ gl,
+__global__ __launch_bounds__(kJoinWaves * kWave) __attribute__((amdgpu_waves_per_eu(2)))
+void k_join_tiles(Req q, const GridLen *__restrict__ gl,
                                                        const uint32_t *__restrict__ gkey,
                                                        const uint32_t *__restrict__ gval,
                                                        const uint8_t *__restrict__ qf,
@@ -280,7 +345,8 @@ __global__ __launch_bounds__(kJoinWaves * kWave) void k_join_tiles(Req q, const 
                                                        int64_t ntiles, int cb1, int cb2,
                                                        double T) {
     __shared__ uint2 queue[kJoinWaves][kQueueCap];
-    __shared__ float4 rowt[kJoinWaves][kJT];          // query coordinates and filter term
+    __shared__ float roww[kJoinWaves][kJT];           // the queries' Gram filter terms
+    __shared__ float4 rowc[kJoinWaves][kJT];          // the queries' principal coordinates
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     const int64_t tile = (int64_t)blockIdx.x * kJoinWaves + wv;
@@ -325,8 +391,8 @@ __global__ __launch_bounds__(kJoinWaves * kWave) void k_join_tiles(Req q, const 
         a = (float)v;
     }
     if (hh == 0) {
-        const float4 c = isq ? gp[kq] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        rowt[wv][i] = make_float4(c.x, c.y, c.z, a);
+        roww[wv][i] = a;
+        rowc[wv][i] = isq ? gp[kq] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -345,63 +411,26 @@ __global__ __launch_bounds__(kJoinWaves * kWave) void k_join_tiles(Req q, const 
         // the queue is written and read by lanes of this wavefront only
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (int base = 0; base < qn; base += kWave) {
-            const int e = base + lane;
-            bool has = false;
-            uint32_t ki = 0, kc = 0;
-            int64_t si = 0, sc = 0;
-            double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0, lim = INFINITY;
-            if (e < qn) {
-                const uint2 pr = queue[wv][e];
-                const int64_t pi_ = pbeg + pr.x, pc_ = pbeg + pr.y;
-                ki = gval[pi_];
-                kc = gval[pc_];
-                if (pc_ != pi_ && !(qf[kc] && pc_ < pi_)) {
-                    si = (int64_t)q.cell[ki] - L.cell_base;
-                    sc = (int64_t)q.cell[kc] - L.cell_base;
-                    const int64_t gap = si > sc ? si - sc : sc - si;
-                    if (gap >= q.excl) {
-                        Pi = bitsd(q.P[ki]);
-                        Pc = bitsd(q.P[kc]);
-                        const double thr = fmin(T, fmax(Pi, Pc));
-                        if (thr > 0.0) {
-                            const float lb = lb_mem<FT>((const FT *)q.F + (int64_t)ki * kRec,
-                                                        (const FT *)q.F + (int64_t)kc * kRec,
-                                                        G.sqrt2m);
-                            if ((double)lb <= T && ((double)lb < Pi || (double)lb < Pc)) {
-                                has = true;
-                                lim = exit_bound(thr);
-                                mui = q.mu[ki];
-                                isi = q.isig[ki];
-                                muc = q.mu[kc];
-                                isc = q.isig[kc];
-                            }
-                        }
-                    }
-                }
-            }
-            const uint64_t mask = __ballot(has);
-            n_kept += e < qn;
-            if (mask)
-                verify_proposals(mask, q.t, si, mui, isi, sc, muc, isc, m, [&](double dd) {
-                    ++n_ver;
-                    const unsigned long long db = (unsigned long long)dbits(dd);
-                    if (dd < Pi) atomicMin((unsigned long long *)&q.P[ki], db);
-                    if (dd < Pc) atomicMin((unsigned long long *)&q.P[kc], db);
-                }, lim);
-        }
+        const uint2 c = join_exact<FT>(q.t, q.cell, q.P, q.F, q.mu, q.isig, gval, qf, queue[wv],
+                                       qn, pbeg, L.cell_base, q.excl, m, G.sqrt2m, T);
+        n_kept += c.x;
+        n_ver += c.y;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         qn = 0;
     };
 
     // walk the candidate runs (one per grid row next to a query's cell) in
-    // tiles of 32; the exact stage runs whenever the queue passes kQueueHigh
-    // and once at the end (one call site)
+    // tiles of 32.  The operands of the next tile are loaded before the
+    // current one goes through the matrix cores and the filter, so that their
+    // latency overlaps that work.  The exact stage runs whenever the queue
+    // passes kQueueHigh and once at the end (one call site).
     int c1p = max(c1min - 1, 0) - 1;
     const int c1end = min(c1max + 1, (int)mask1);
     int64_t c0 = 0, cend = 0;
-    for (;;) {
+    // move [c0, cend) to the next non-empty run once the current one is used
+    // up (uniform); false when there is none
+    auto next_run = [&]() -> bool {
         if (cb2 == 0) {
             // one coordinate: the cells next to the queries' cells form a
             // single run of the order
@@ -423,54 +452,74 @@ __global__ __launch_bounds__(kJoinWaves * kWave) void k_join_tiles(Req q, const 
                 cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c2hi) + 1u);
             }
         }
-        const bool have = c0 < cend;
+        return c0 < cend;
+    };
+    // a candidate tile's operands: lane (i, hh) holds candidate c0 + i
+    struct CandTile {
+        int64_t pc;
+        bool qc;
+        float bj;
+        float4 gc;
+        bf16x8 bH0, bH1, bL0, bL1;
+    };
+    auto load_tile = [&](bool have_t) {
+        CandTile t;
+        t.pc = c0 + i;
+        const bool validc = have_t && t.pc < cend;
+        const uint32_t kc = validc ? gval[t.pc] : 0u;
+        t.gc = validc ? gp[kc] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        t.qc = validc && qf[kc];
+        const uint4 *o = jop + (int64_t)kc * 8;
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        t.bH0 = as_bf16x8(validc ? o[hh] : z);
+        t.bH1 = as_bf16x8(validc ? o[2 + hh] : z);
+        t.bL0 = as_bf16x8(validc ? o[4 + hh] : z);
+        t.bL1 = as_bf16x8(validc ? o[6 + hh] : z);
+        t.bj = validc ? (float)(0.5 * (double)jmeta[kc].x * (1.0 - 0x1.0p-23)) : INFINITY;
+        return t;
+    };
+    bool have = next_run();
+    CandTile cur = load_tile(have);
+    for (;;) {
         if (qn > (have ? kQueueHigh : 0)) flush();
         if (!have) break;
-        const int64_t pc = c0 + i;
-        const bool validc = pc < cend;
-        const uint32_t kc = validc ? gval[pc] : 0u;
-        bf16x8 bH0, bH1, bL0, bL1;
-        float bj = INFINITY;
-        const float4 gc = validc ? gp[kc] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const bool qc = validc && qf[kc];
-        {
-            const uint4 *o = jop + (int64_t)kc * 8;
-            const uint4 z = make_uint4(0, 0, 0, 0);
-            bH0 = as_bf16x8(validc ? o[hh] : z);
-            bH1 = as_bf16x8(validc ? o[2 + hh] : z);
-            bL0 = as_bf16x8(validc ? o[4 + hh] : z);
-            bL1 = as_bf16x8(validc ? o[6 + hh] : z);
-            if (validc) bj = (float)(0.5 * (double)jmeta[kc].x * (1.0 - 0x1.0p-23));
-        }
+        // the next tile's position and loads first
+        c0 += kJT;
+        const bool have_n = next_run();
+        const CandTile nxt = load_tile(have_n);
         f32x16 acc = {};
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bH0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bH1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bL0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bL1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, bH0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, bH1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, cur.bH0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, cur.bH1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, cur.bL0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, cur.bL1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, cur.bH0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, cur.bH1, acc, 0, 0, 0);
         n_pairs += 16;
         // keep (row, candidate) unless the Gram bound or a coordinate rules it
         // out, or the candidate is a query earlier in the order (its tile
-        // takes the pair), or it is the row itself
+        // takes the pair), or it is the row itself.  Positions relative to
+        // the tile (p0) and to the length (pbeg) fit 32 bits.
         asm volatile("" ::: "memory");   // read the row table per tile, not once
+        const int pcr = (int)(cur.pc - p0);
+        const uint32_t pcl = (uint32_t)(cur.pc - pbeg), p0l = (uint32_t)(p0 - pbeg);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             // the rows of the 32 x 32 result this lane holds: 8 (r / 4) + 4 hh + r % 4
             const int row = 8 * (r / 4) + 4 * hh + (r % 4);
-            const float4 rt = rowt[wv][row];
-            const int64_t prow = p0 + row;
-            const bool keep = acc[r] >= rt.w + bj && fabsf(rt.x - gc.x) <= G.rp &&
-                              fabsf(rt.y - gc.y) <= G.rp && fabsf(rt.z - gc.z) <= G.rp &&
-                              pc != prow && !(qc && pc < prow);
+            const bool gram = acc[r] >= roww[wv][row] + cur.bj;
+            if (__ballot(gram) == 0) continue;
+            const float4 rc = rowc[wv][row];
+            const bool keep = gram && fabsf(rc.x - cur.gc.x) <= G.rp &&
+                              fabsf(rc.y - cur.gc.y) <= G.rp && fabsf(rc.z - cur.gc.z) <= G.rp &&
+                              pcr != row && !(cur.qc && pcr < row);
             const uint64_t bal = __ballot(keep);
             if (bal == 0) continue;
             if (keep)
-                queue[wv][qn + __popcll(bal & lanemask_lt())] =
-                    make_uint2((uint32_t)(prow - pbeg), (uint32_t)(pc - pbeg));
+                queue[wv][qn + __popcll(bal & lanemask_lt())] = make_uint2(p0l + (uint32_t)row, pcl);
             qn += __popcll(bal);
         }
-        c0 += kJT;
+        cur = nxt;
+        have = have_n;
     }
     // statistics: one atomic per wavefront
     for (int off = kWave / 2; off > 0; off >>= 1) {

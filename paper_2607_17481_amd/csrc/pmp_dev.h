@@ -328,13 +328,13 @@ __device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__r
 // one per group of kGroup lanes (group_zdist).  Both give the same bits.
 // `on_result(d)` runs on the proposing lane with its snapped distance (+inf
 // when the sum stopped early).
-template <typename F>
+template <bool kLaneForm = true, typename F>
 __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__restrict__ t,
                                                  int64_t a, double mua, double ia, int64_t b,
                                                  double mub, double ib, int m, F &&on_result,
                                                  double lim2 = INFINITY) {
     const int lane = lane_id();
-    if (__popcll(mask) >= kLaneMode &&
+    if (kLaneForm && __popcll(mask) >= kLaneMode &&
         __shfl(m, __ffsll((unsigned long long)mask) - 1, kWave) <= kLaneModeMaxM) {
         // most lanes propose short windows: each evaluates its own pair
         if ((mask >> lane) & 1ull) on_result(snap(lane_zdist(t, a, mua, ia, b, mub, ib, m, lim2)));
