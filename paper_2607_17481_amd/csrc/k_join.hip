@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
                                                       uint32_t *__restrict__ gkey,
                                                       uint32_t *__restrict__ gval,
                                                       uint8_t *__restrict__ qf,
-                                                      const float4 *__restrict__ gp) {
+                                                      float4 *__restrict__ gp) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
     const int64_t k_first = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
@@ -260,7 +260,11 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
     };
     gkey[k] = ((uint32_t)l << (cb1 + cb2)) | (cell(p1, cb1) << cb2) | (cb2 ? cell(p2, cb2) : 0u);
     gval[k] = (uint32_t)k;
-    qf[k] = q.P[k] != 0ull;
+    const bool f = q.P[k] != 0ull;
+    qf[k] = f;
+    // the same flag in the sign of the candidate's Gram term, so that a
+    // candidate tile reads one 16-byte word per window besides its operands
+    gp[k].w = f ? -fabsf(c.w) : fabsf(c.w);
 }
 
 // ------------------------------------------------------------ the tiles
@@ -454,7 +458,9 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
         }
         return c0 < cend;
     };
-    // a candidate tile's operands: lane (i, hh) holds candidate c0 + i
+    // a candidate tile's operands: lane (i, hh) holds candidate c0 + i.  The
+    // loads run two deep: a tile's positions (gval) two tiles ahead of its
+    // use, its operands one tile ahead.
     struct CandTile {
         int64_t pc;
         bool qc;
@@ -462,31 +468,42 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
         float4 gc;
         bf16x8 bH0, bH1, bL0, bL1;
     };
-    auto load_tile = [&](bool have_t) {
+    auto load_tile = [&](bool validc, int64_t pc, uint32_t kc) {
         CandTile t;
-        t.pc = c0 + i;
-        const bool validc = have_t && t.pc < cend;
-        const uint32_t kc = validc ? gval[t.pc] : 0u;
-        t.gc = validc ? gp[kc] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        t.qc = validc && qf[kc];
+        t.pc = pc;
+        t.gc = validc ? gp[kc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
         const uint4 *o = jop + (int64_t)kc * 8;
         const uint4 z = make_uint4(0, 0, 0, 0);
         t.bH0 = as_bf16x8(validc ? o[hh] : z);
         t.bH1 = as_bf16x8(validc ? o[2 + hh] : z);
         t.bL0 = as_bf16x8(validc ? o[4 + hh] : z);
         t.bL1 = as_bf16x8(validc ? o[6 + hh] : z);
-        t.bj = validc ? (float)(0.5 * (double)jmeta[kc].x * (1.0 - 0x1.0p-23)) : INFINITY;
+        t.bj = fabsf(t.gc.w);
+        t.qc = validc && signbit(t.gc.w);
         return t;
     };
+    // tile 0 (current) and tile 1 (next) positions; the iterator then
+    // stands on tile 1
     bool have = next_run();
-    CandTile cur = load_tile(have);
+    const int64_t pc0 = c0 + i;
+    const bool v0 = have && pc0 < cend;
+    const uint32_t kc0 = v0 ? gval[pc0] : 0u;
+    c0 += kJT;
+    bool have1 = have && next_run();
+    int64_t pc1 = c0 + i;
+    bool v1 = have1 && pc1 < cend;
+    uint32_t kc1 = v1 ? gval[pc1] : 0u;
+    CandTile cur = load_tile(v0, pc0, kc0);
     for (;;) {
         if (qn > (have ? kQueueHigh : 0)) flush();
         if (!have) break;
-        // the next tile's position and loads first
+        // positions of the tile after next, operands of the next tile
         c0 += kJT;
-        const bool have_n = next_run();
-        const CandTile nxt = load_tile(have_n);
+        const bool have2 = have1 && next_run();
+        const int64_t pc2 = c0 + i;
+        const bool v2 = have2 && pc2 < cend;
+        const uint32_t kc2 = v2 ? gval[pc2] : 0u;
+        const CandTile nxt = load_tile(v1, pc1, kc1);
         f32x16 acc = {};
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, cur.bH0, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, cur.bH1, acc, 0, 0, 0);
@@ -519,7 +536,11 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
             qn += __popcll(bal);
         }
         cur = nxt;
-        have = have_n;
+        have = have1;
+        have1 = have2;
+        pc1 = pc2;
+        v1 = v2;
+        kc1 = kc2;
     }
     // statistics: one atomic per wavefront
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -549,7 +570,7 @@ void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hi
 }
 
 void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2,
-                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, const float4 *gp,
+                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
                       hipStream_t s) {
     if (N <= 0) return;
     hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1, cb2, gkey,

@@ -710,7 +710,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
             p1 = fma(sm.u[1][c], (double)f[c], p1);
             p2 = fma(sm.u[2][c], (double)f[c], p2);
         }
-        q.gp[kk] = make_float4((float)p0, (float)p1, (float)p2, 0.0f);
+        // w: the join's candidate Gram term 0.5 |G|^2, rounded down (its sign
+        // bit is set per certify round by the grid keys)
+        q.gp[kk] = make_float4((float)p0, (float)p1, (float)p2,
+                               (float)(0.5 * (double)(float)n2 * (1.0 - 0x1.0p-23)));
     }
     const double ep = ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
     q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),

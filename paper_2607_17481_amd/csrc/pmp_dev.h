@@ -64,7 +64,8 @@ struct Req {
     uint64_t *keyw;        // [N] key word: signature | probe order << 24
     uint4   *jop;          // [N][8] join operands: 32 bf16 hi, then 32 bf16 lo (G = hi + lo)
     float4  *jmeta;        // [N] |G|^2, e' >= |G - F|, bound on |G|, 0
-    float4  *gp;           // [N] principal coordinates of the FP32 feature copy, 0
+    float4  *gp;           // [N] principal coordinates of the FP32 feature copy, and
+                           //     0.5 |G|^2 (rounded down) with the sign bit = (P != 0)
     const double *udir;    // [L][kJoinDirs][32] principal directions (null: none)
     // bucket order (slots)
     uint32_t *skey;        // [N] sort keys
@@ -424,7 +425,7 @@ size_t join_cov_doubles(int L);
 // principal directions: covariance of a sample, then power iteration (GPU)
 void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s);
 void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2,
-                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, const float4 *gp,
+                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
                       hipStream_t s);
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
