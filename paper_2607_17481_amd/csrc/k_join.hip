@@ -323,7 +323,8 @@ __device__ __forceinline__ uint2 join_exact(const double *__restrict__ t,
         const uint64_t mask = __ballot(has);
         n_kept += e < qn;
         if (mask)
-            verify_proposals<false>(mask, t, si, mui, isi, sc, muc, isc, m, [&](double dd) {
+            verify_proposals<false>(mask, SeriesA{t}, t, si, mui, isi, sc, muc, isc, m,
+                                    [&](double dd) {
                 ++n_ver;
                 const unsigned long long db = (unsigned long long)dbits(dd);
                 if (dd < Pi) atomicMin((unsigned long long *)&P[ki], db);

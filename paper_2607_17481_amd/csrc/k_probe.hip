@@ -33,14 +33,27 @@
 
 namespace pmp {
 
+// The query windows of a wavefront, staged in LDS when they share one length
+// and lie within a short span of the series (dynamic size: kQwinExtra + the
+// longest window, in doubles).  The staged samples are the series' own, so a
+// distance read through them has the same bits.
+extern __shared__ double probe_qwin[];
+constexpr int kQwinExtra = 256;
+struct QwinA {
+    int64_t base;
+    __device__ __forceinline__ double operator()(int64_t x) const { return probe_qwin[x - base]; }
+};
+
 // Queries are taken in (length, start) order (indexed position k), so that
 // neighbouring windows, which tend to cost alike, share a wavefront.  A block
 // is one wavefront: wavefront times vary over two orders of magnitude, and a
 // single-wave block lets a compute unit start new work as soon as any one
 // wavefront ends, not when a slot for four is free.
+// Four wavefronts per SIMD (128 registers, a few spilled) hide more of the
+// candidate chain's latency than three without spills.
 template <typename FT>
-__global__ __launch_bounds__(kWave) void k_probe(Req q, const uint32_t *__restrict__ bstart,
-                                                  int64_t N) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4)))
+void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
     const int64_t k_first = (int64_t)blockIdx.x * kWave;
     const int64_t k = k_first + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
@@ -48,7 +61,7 @@ __global__ __launch_bounds__(kWave) void k_probe(Req q, const uint32_t *__restri
 
     // ---- per-lane query state
     bool done = k >= N;
-    int m = 0, d = 0, probes = 0;
+    int l = -1, m = 0, d = 0, probes = 0;
     int64_t cell_base = 0;
     uint32_t cq = 0, prefix = 0, lim = 0;
     int64_t iq = 0;
@@ -58,7 +71,7 @@ __global__ __launch_bounds__(kWave) void k_probe(Req q, const uint32_t *__restri
     const uint32_t *bb = bstart;
     const FT *fq = (const FT *)q.F;
     if (!done) {
-        const int l = find_len_k_wave(q.len, q.L, k_first, k);
+        l = find_len_k_wave(q.len, q.L, k_first, k);
         const LenInfo L = q.len[l];
         m = L.m;
         d = L.depth;
@@ -77,6 +90,23 @@ __global__ __launch_bounds__(kWave) void k_probe(Req q, const uint32_t *__restri
         fq += k * kRec;
         done = Pq == 0.0 || iq - q.excl < 0;
         lim = (uint32_t)(cell_base + iq - q.excl);
+    }
+    // ---- stage the query windows (uniform decision): one length, and the
+    // span from the first start to the last window's end fits
+    bool staged = false;
+    int64_t qlo = 0;
+    {
+        const uint64_t valid = __ballot(l >= 0);
+        const int last = 63 - __clzll((long long)valid);
+        const int l0 = __shfl(l, 0, kWave);
+        qlo = __shfl(iq, 0, kWave);
+        const int64_t qhi = __shfl(iq, last, kWave) + __shfl(m, last, kWave);
+        staged = __ballot(l >= 0 && l != l0) == 0 && qhi - qlo <= (int64_t)qcap;
+        if (staged) {
+            for (int64_t x = lane_id(); x < qhi - qlo; x += kWave) probe_qwin[x] = q.t[qlo + x];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     // candidate iterator
     int pr = -1, budget = q.budget_R;
@@ -144,19 +174,22 @@ __global__ __launch_bounds__(kWave) void k_probe(Req q, const uint32_t *__restri
         // ---- the wavefront verifies the proposals, four at a time
         const uint64_t mask = __ballot(has);
         if (mask == 0) break;
-        verify_proposals(mask, q.t, iq, muq, isq, pic, pmu, pis, m,
-                         [&](double dd) {
-                             ++n_ver;
-                             const unsigned long long db = (unsigned long long)dbits(dd);
-                             if (dd < Pq) {
-                                 atomicMin((unsigned long long *)&q.P[k], db);
-                                 Pq = dd;
-                             }
-                             if (dd < pPc) atomicMin((unsigned long long *)&q.P[pc], db);
-                             has = false;
-                             if (Pq == 0.0) done = true;
-                         },
-                         plim);
+        auto on_result = [&](double dd) {
+            ++n_ver;
+            const unsigned long long db = (unsigned long long)dbits(dd);
+            if (dd < Pq) {
+                atomicMin((unsigned long long *)&q.P[k], db);
+                Pq = dd;
+            }
+            if (dd < pPc) atomicMin((unsigned long long *)&q.P[pc], db);
+            has = false;
+            if (Pq == 0.0) done = true;
+        };
+        if (staged)
+            verify_proposals(mask, QwinA{qlo}, q.t, iq, muq, isq, pic, pmu, pis, m, on_result, plim);
+        else
+            verify_proposals(mask, SeriesA{q.t}, q.t, iq, muq, isq, pic, pmu, pis, m, on_result,
+                             plim);
     }
     // stats: one atomic per wave
     unsigned long long a = n_cand, v = n_ver;
@@ -183,13 +216,16 @@ __global__ __launch_bounds__(kBlock) void k_hot_buckets(const uint32_t *__restri
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, hipStream_t s) {
+void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, int max_m,
+                  hipStream_t s) {
     if (N <= 0) return;
     const dim3 grid((unsigned)((N + kWave - 1) / kWave));
+    const int qcap = kQwinExtra + max_m;
+    const size_t lds = (size_t)qcap * sizeof(double);
     if (precision == 0)
-        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), 0, s, q, bstart, N);
+        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), lds, s, q, bstart, N, qcap);
     else
-        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), 0, s, q, bstart, N);
+        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), lds, s, q, bstart, N, qcap);
 }
 
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,

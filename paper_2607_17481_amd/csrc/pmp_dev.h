@@ -169,9 +169,18 @@ constexpr int kLaneModeMaxM = 100;        // for windows up to this length: long
                                           // read better in groups (contiguous loads);
                                           // measured crossover between 100 and 124
 
-__device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
-                                              double ia, int64_t b, double mub, double ib, int m,
-                                              double lim2 = INFINITY) {
+// The first window's samples are read through an accessor: the series
+// itself, or a copy of the same samples staged in LDS; the second window's
+// come from the series.
+struct SeriesA {
+    const double *t;
+    __device__ __forceinline__ double operator()(int64_t x) const { return t[x]; }
+};
+
+template <class A>
+__device__ __forceinline__ double group_zdist_a(A qa, const double *__restrict__ t, int64_t a,
+                                                double mua, double ia, int64_t b, double mub,
+                                                double ib, int m, double lim2 = INFINITY) {
 #pragma clang fp contract(off)
     double acc = 0.0;
     // kZBatch terms per lane are loaded before they are summed (in order), so
@@ -181,7 +190,7 @@ __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int6
 #pragma unroll
         for (int u = 0; u < kZBatch; ++u) {
             const int r = r0 + u * kGroup;
-            xa[u] = r < m ? t[a + r] : 0.0;
+            xa[u] = r < m ? qa(a + r) : 0.0;
             xb[u] = r < m ? t[b + r] : 0.0;
         }
 #pragma unroll
@@ -208,6 +217,11 @@ __device__ __forceinline__ double group_zdist(const double *__restrict__ t, int6
     for (int off = 1; off < kGroup; off <<= 1) acc += __shfl_xor(acc, off, kGroup);
     return sqrt(acc);
 }
+__device__ __forceinline__ double group_zdist(const double *__restrict__ t, int64_t a, double mua,
+                                              double ia, int64_t b, double mub, double ib, int m,
+                                              double lim2 = INFINITY) {
+    return group_zdist_a(SeriesA{t}, t, a, mua, ia, b, mub, ib, m, lim2);
+}
 
 // The same canonical distance evaluated by one lane alone, bit for bit: the
 // kGroup partial sums of group_zdist become kGroup accumulators of the lane
@@ -218,9 +232,10 @@ static_assert(kGroup == 8, "lane_zdist combines eight partial sums");
 __device__ __forceinline__ double butterfly8(const double *p) {
     return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
 }
-__device__ __forceinline__ double lane_zdist(const double *__restrict__ t, int64_t a, double mua,
-                                             double ia, int64_t b, double mub, double ib, int m,
-                                             double lim2 = INFINITY) {
+template <class A>
+__device__ __forceinline__ double lane_zdist_a(A qa, const double *__restrict__ t, int64_t a,
+                                               double mua, double ia, int64_t b, double mub,
+                                               double ib, int m, double lim2 = INFINITY) {
 #pragma clang fp contract(off)
     double acc[kGroup];
 #pragma unroll
@@ -229,7 +244,7 @@ __device__ __forceinline__ double lane_zdist(const double *__restrict__ t, int64
         double xa[kGroup], xb[kGroup];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-            xa[g] = r0 + g < m ? t[a + r0 + g] : 0.0;
+            xa[g] = r0 + g < m ? qa(a + r0 + g) : 0.0;
             xb[g] = r0 + g < m ? t[b + r0 + g] : 0.0;
         }
 #pragma unroll
@@ -248,6 +263,11 @@ __device__ __forceinline__ double lane_zdist(const double *__restrict__ t, int64
             return INFINITY;
     }
     return sqrt(butterfly8(acc));
+}
+__device__ __forceinline__ double lane_zdist(const double *__restrict__ t, int64_t a, double mua,
+                                             double ia, int64_t b, double mub, double ib, int m,
+                                             double lim2 = INFINITY) {
+    return lane_zdist_a(SeriesA{t}, t, a, mua, ia, b, mub, ib, m, lim2);
 }
 
 // Squared bound for group_zdist's early exit: a sum that reaches it has a
@@ -329,8 +349,8 @@ __device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__r
 // one per group of kGroup lanes (group_zdist).  Both give the same bits.
 // `on_result(d)` runs on the proposing lane with its snapped distance (+inf
 // when the sum stopped early).
-template <bool kLaneForm = true, typename F>
-__device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__restrict__ t,
+template <bool kLaneForm = true, class A, typename F>
+__device__ __forceinline__ void verify_proposals(uint64_t mask, A qa, const double *__restrict__ t,
                                                  int64_t a, double mua, double ia, int64_t b,
                                                  double mub, double ib, int m, F &&on_result,
                                                  double lim2 = INFINITY) {
@@ -338,7 +358,8 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__
     if (kLaneForm && __popcll(mask) >= kLaneMode &&
         __shfl(m, __ffsll((unsigned long long)mask) - 1, kWave) <= kLaneModeMaxM) {
         // most lanes propose short windows: each evaluates its own pair
-        if ((mask >> lane) & 1ull) on_result(snap(lane_zdist(t, a, mua, ia, b, mub, ib, m, lim2)));
+        if ((mask >> lane) & 1ull)
+            on_result(snap(lane_zdist_a(qa, t, a, mua, ia, b, mub, ib, m, lim2)));
         return;
     }
     const int grp = lane / kGroup;
@@ -368,7 +389,7 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, const double *__
         const double glim = __shfl(lim2, my, kWave);
         int gm = __shfl(m, my, kWave);
         if (!live) gm = 0;
-        const double d = snap(group_zdist(t, ga, gmua, gia, gb, gmub, gib, gm, glim));
+        const double d = snap(group_zdist_a(qa, t, ga, gmua, gia, gb, gmub, gib, gm, glim));
         // hand each result back to its proposing lane
 #pragma unroll
         for (int g = 0; g < kPerRound; ++g) {
@@ -408,7 +429,8 @@ void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *b
 void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);
 void launch_invert(const uint32_t *perm, int64_t N, uint32_t *inv, hipStream_t s);
 // (k_probe.hip)
-void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, hipStream_t s);
+void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, int max_m,
+                  hipStream_t s);
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,
                         hipStream_t s);
 // (k_certify.hip)

@@ -761,7 +761,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
     tm.mark(3, s);
     tm.mark(4, s);
-    launch_probe(o.precision, q, b.bstart, N, s);
+    launch_probe(o.precision, q, b.bstart, N, p.max_m, s);
     tm.mark(5, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
