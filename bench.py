@@ -154,10 +154,11 @@ SERVING_DEFAULT = {"requests": 96, "n_lo": 10_000, "n_hi": 500_000, "slots": 4,
                    "hbm_budget_gb": 96}
 
 
-def serving_run(precision, reqs, series, rate, slots, budget):
+def serving_run(precision, reqs, series, rate, slots, budget, progress=False):
     """Open loop: each request is submitted at its Poisson arrival time; the
     server admits it when a slot and HBM budget are free.  Latency is the
-    library's clock from submission to results in host memory."""
+    library's clock from submission to results in host memory.  With
+    `progress`, every tenth completed request is reported on stderr."""
     import threading
     from paper_2607_17481_amd import pmp
     opts = pmp.options(precision=precision)
@@ -172,6 +173,8 @@ def serving_run(precision, reqs, series, rate, slots, budget):
                 if i < len(ids):
                     results[i] = srv.wait(ids[i])[1]
                     i += 1
+                    if progress and i % 10 == 0:
+                        print(f"  {i}/{len(reqs)} done", file=sys.stderr, flush=True)
                 else:
                     time.sleep(0.001)
             done.set()
@@ -221,13 +224,13 @@ def serving_sweep(cfg):
     reqs = synth.serving_requests(cfg["requests"], 1.0, cfg["n_lo"], cfg["n_hi"])
     series = [r.series() for r in reqs]
     budget = cfg["hbm_budget_gb"] << 30
-    cap = serving_run(0, reqs, series, 0.0, cfg["slots"], budget)["req_per_s"]
+    cap = serving_run(0, reqs, series, 0.0, cfg["slots"], budget, True)["req_per_s"]
     print(f"capacity {cap:.3f} req/s", file=sys.stderr, flush=True)
     out = {"metric": "serving latency over offered load", "form": "fp64",
            "requests": len(reqs), "n_range": [cfg["n_lo"], cfg["n_hi"]], "slots": cfg["slots"],
            "hbm_budget_gb": cfg["hbm_budget_gb"], "capacity_req_per_s": cap, "loads": {}}
     for f in cfg["loads"]:
-        r = serving_run(0, reqs, series, f * cap, cfg["slots"], budget)
+        r = serving_run(0, reqs, series, f * cap, cfg["slots"], budget, True)
         r["offered_req_per_s"] = f * cap
         out["loads"][str(f)] = r
         print(f"load {f}: p50 {r['p50_ms']:.0f} ms p99 {r['p99_ms']:.0f} ms", file=sys.stderr,
