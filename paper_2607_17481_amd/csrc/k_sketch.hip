@@ -101,6 +101,7 @@ constexpr int kStageLd = 31;                  // doubles per staged row (odd: th
 
 struct SketchSmem {
     int32_t kpos[kTileW];                     // indexed position, -1: constant window
+    uint16_t widx[kTileW];                    // the tile's non-constant windows, in order
     uint8_t rows[kSegW / kSlidesC][kRowsC];   // indexed staging rows of each chunk
     int32_t nrows[kSegW / kSlidesC];
     float ymax[kSegs];                        // largest |t - c| of each segment
@@ -162,13 +163,14 @@ __device__ __forceinline__ void sketch_record(const Req &q, int m, int kprime,
 
 // Shared first steps of a sketch tile (samples already in LDS): the
 // compacted position k of every non-constant window (thread tid takes
-// windows 4 tid .. 4 tid + 3; a block scan), and the two-pass moments of
-// those windows (Sec. 3.2), one thread per window, with their cell and the
-// initial profile value.  Ends with the block synchronized and kpos final.
+// windows 4 tid .. 4 tid + 3; a block scan) and the list of those windows,
+// then their two-pass moments (Sec. 3.2), dealt evenly over the threads from
+// the list, with their cell and the initial profile value.  Ends with the
+// block synchronized and kpos final.
 __device__ __forceinline__ void tile_positions_and_moments(
     const Req &q, const LenInfo &L, int64_t i0, int nw, int64_t tile, const double *st,
     const uint32_t *__restrict__ E, const uint32_t *__restrict__ tile_off, int32_t *kpos,
-    uint32_t *wsum) {
+    uint16_t *widx, uint32_t *wsum) {
     const int m = L.m;
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -190,21 +192,27 @@ __device__ __forceinline__ void tile_positions_and_moments(
         }
         if (lane == kWave - 1) wsum[wv] = (uint32_t)x;
         __syncthreads();
-        uint32_t pos = tile_off[tile] + (uint32_t)(x - c);
-        for (int v = 0; v < wv; ++v) pos += wsum[v];
+        uint32_t loc = (uint32_t)(x - c);
+        for (int v = 0; v < wv; ++v) loc += wsum[v];
+        const uint32_t base = tile_off[tile];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int w = 4 * tid + j;
-            if (w < nw) kpos[w] = ix[j] ? (int32_t)pos++ : -1;
+            if (w < nw) {
+                kpos[w] = ix[j] ? (int32_t)(base + loc) : -1;
+                if (ix[j]) widx[loc++] = (uint16_t)w;
+            }
         }
     }
     __syncthreads();
+    int nix = 0;                                        // non-constant windows of the tile
+    for (int v = 0; v < kBlock / kWave; ++v) nix += (int)wsum[v];
 
     // ---- moments (two-pass, population; Sec. 3.2), one thread per
     // non-constant window; four partial sums keep the LDS loads independent
-    for (int w = tid; w < nw; w += kBlock) {
+    for (int xi = tid; xi < nix; xi += kBlock) {
+        const int w = widx[xi];
         const int32_t kk = kpos[w];
-        if (kk < 0) continue;
         const double *x = st + w;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int r = 0;
@@ -286,7 +294,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     for (int x = tid; x < kRowsC * (kFD - 2 * kp); x += kBlock)
         stage[x / (kFD - 2 * kp)][2 * kp + x % (kFD - 2 * kp)] = 0.0;
 
-    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, sm.kpos, sm.wsum);
+    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, sm.kpos, sm.widx, sm.wsum);
     // ---- per chunk, the staging rows that hold a non-constant window;
     // wavefront wv lists chunks 2 wv and 2 wv + 1 (row = segment * 8 + slide)
 #pragma unroll
@@ -469,6 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *_
                                                         const uint16_t *__restrict__ bl) {
     extern __shared__ double dyn[];
     __shared__ int32_t kpos[kTileW];
+    __shared__ uint16_t widx[kTileW];
     __shared__ uint32_t wsum[kBlock / kWave];
     __shared__ int emax_s;
     const int64_t tile = blockIdx.x;
@@ -485,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *_
 
     if (tid == 0) emax_s = 0;
     for (int r = tid; r < nw + mp + kMBlk; r += kBlock) st[r] = r < nw + m - 1 ? q.t[i0 + r] : 0.0;
-    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, wsum);
+    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, widx, wsum);
 
     const uint4 *Bh = (const uint4 *)(bh + bbase[l]);
     const uint4 *Bl = (const uint4 *)(bl + bbase[l]);
