@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -107,6 +109,26 @@ static double gauss(uint64_t seed, int m, int l, int c) {
 
 constexpr int kFD = 2 * (kMaxK - 1);   // 30 feature reals
 
+// The SimHash projections of one length (kMaxBits x 30, a pure function of
+// the seed and m) into out, from a table kept across requests: a request
+// over 51 lengths needs 36,720 Gaussian draws, about 1.7 ms of host time
+// while the GPU would wait.  The table is bounded (cleared past 8192
+// lengths) and shared by the server's threads.
+static void projections(uint64_t seed, int m, float *out) {
+    static std::mutex mu;
+    static std::map<std::pair<uint64_t, int>, std::vector<float>> table;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = table.find({seed, m});
+    if (it == table.end()) {
+        if (table.size() >= 8192) table.clear();
+        std::vector<float> v((size_t)kMaxBits * kFD);
+        for (int l = 0; l < kMaxBits; ++l)
+            for (int c = 0; c < kFD; ++c) v[(size_t)l * kFD + c] = (float)gauss(seed, m, l, c);
+        it = table.emplace(std::make_pair(seed, m), std::move(v)).first;
+    }
+    std::memcpy(out, it->second.data(), it->second.size() * sizeof(float));
+}
+
 static int kprime_of(int K, int m) {
     int half = (m + 1) / 2 - 1;
     int kp = std::min(K - 1, half);
@@ -123,16 +145,29 @@ static int kprime_of(int K, int m) {
 static int calibrate(const std::vector<std::vector<std::vector<double>>> &sets,
                      const std::vector<int> &ms, int64_t n, int alpha, int gamma, int B) {
     const double eta = 0.85;
-    struct W { std::vector<double> re, im; };
-    std::vector<std::vector<W>> spec(sets.size());
+    // per sampled window: prefix sums over the bins k = 1..K' of its energy
+    // (e[k]), and per consecutive pair those of the dot product and of both
+    // energies, so that each candidate K costs O(1) per window and pair
+    struct Spec { double re[kMaxK], im[kMaxK]; };
+    std::vector<std::vector<Spec>> spec(sets.size());
     for (size_t s = 0; s < sets.size(); ++s) {
         const int m = ms[s];
-        // twiddles cos, sin (2 pi j / m), j < m
+        const int kp = kprime_of(kMaxK, m);
+        // twiddles cos, sin (2 pi j / m), j < m, laid out per sample r for
+        // the bins 1..K' (bin k at r uses j = k r mod m)
         std::vector<double> tc(m), ts(m);
         for (int j = 0; j < m; ++j) {
             tc[j] = std::cos(6.283185307179586 * (double)j / m);
             ts[j] = std::sin(6.283185307179586 * (double)j / m);
         }
+        std::vector<double> cr((size_t)m * kMaxK, 0.0), sr((size_t)m * kMaxK, 0.0);
+        for (int r = 0; r < m; ++r)
+            for (int k = 1; k <= kp; ++k) {
+                const int j = (int)(((int64_t)k * r) % m);
+                cr[(size_t)r * kMaxK + k] = tc[j];
+                sr[(size_t)r * kMaxK + k] = ts[j];
+            }
+        std::vector<double> zw(m);
         for (const auto &w : sets[s]) {
             double mu = 0.0;
             for (double x : w) mu += x;
@@ -141,58 +176,85 @@ static int calibrate(const std::vector<std::vector<std::vector<double>>> &sets,
             for (double x : w) q += (x - mu) * (x - mu);
             const double sg = std::sqrt(q / m);
             if (!(sg > 0.0)) continue;
-            W f;
-            f.re.assign(kMaxK, 0.0);
-            f.im.assign(kMaxK, 0.0);
-            const int kp = kprime_of(kMaxK, m);
-            for (int k = 1; k <= kp; ++k) {
-                double re = 0.0, im = 0.0;
-                int j = 0;                       // (k r) mod m
-                for (int r = 0; r < m; ++r) {
-                    const double z = (w[r] - mu) / sg;
-                    re += z * tc[j];
-                    im -= z * ts[j];
-                    j += k;
-                    if (j >= m) j -= m;
+            for (int r = 0; r < m; ++r) zw[r] = (w[r] - mu) / sg;
+            Spec f;
+            for (int k = 0; k < kMaxK; ++k) f.re[k] = f.im[k] = 0.0;
+            // every bin sums its terms in ascending r
+            for (int r = 0; r < m; ++r) {
+                const double z = zw[r];
+                const double *c = &cr[(size_t)r * kMaxK], *sn = &sr[(size_t)r * kMaxK];
+                for (int k = 1; k < kMaxK; ++k) {
+                    f.re[k] += z * c[k];
+                    f.im[k] -= z * sn[k];
                 }
-                f.re[k] = re;
-                f.im[k] = im;
             }
-            spec[s].push_back(std::move(f));
+            spec[s].push_back(f);
         }
+    }
+    struct Pre { std::vector<double> e; std::vector<double> ab, aa, bb; std::vector<char> dup; };
+    std::vector<Pre> pre(sets.size());
+    for (size_t s = 0; s < sets.size(); ++s) {
+        const auto &v = spec[s];
+        const int kpf = kprime_of(kMaxK, ms[s]);
+        Pre &P = pre[s];
+        P.e.assign((size_t)v.size() * (kMaxK + 1), 0.0);
+        for (size_t w = 0; w < v.size(); ++w)
+            for (int k = 1; k <= kMaxK; ++k)
+                P.e[w * (kMaxK + 1) + k] = P.e[w * (kMaxK + 1) + k - 1] +
+                    (k < kMaxK ? v[w].re[k] * v[w].re[k] + v[w].im[k] * v[w].im[k] : 0.0);
+        const size_t np = v.size() > 0 ? v.size() - 1 : 0;
+        P.ab.assign(np * (kMaxK + 1), 0.0);
+        P.aa.assign(np * (kMaxK + 1), 0.0);
+        P.bb.assign(np * (kMaxK + 1), 0.0);
+        P.dup.assign(np, 0);
+        for (size_t w = 0; w < np; ++w) {
+            double ab = 0.0, aa = 0.0, bb = 0.0;
+            for (int k = 1; k <= kMaxK; ++k) {
+                if (k < kMaxK) {
+                    ab += v[w].re[k] * v[w + 1].re[k] + v[w].im[k] * v[w + 1].im[k];
+                    aa += v[w].re[k] * v[w].re[k] + v[w].im[k] * v[w].im[k];
+                    bb += v[w + 1].re[k] * v[w + 1].re[k] + v[w + 1].im[k] * v[w + 1].im[k];
+                }
+                P.ab[w * (kMaxK + 1) + k] = ab;
+                P.aa[w * (kMaxK + 1) + k] = aa;
+                P.bb[w * (kMaxK + 1) + k] = bb;
+            }
+        }
+        auto angle = [&](size_t w, int kk) {
+            const double ab = P.ab[w * (kMaxK + 1) + kk], aa = P.aa[w * (kMaxK + 1) + kk],
+                         bb = P.bb[w * (kMaxK + 1) + kk];
+            if (!(aa > 0.0 && bb > 0.0)) return 0.0;
+            double c = ab / std::sqrt(aa * bb);
+            c = std::max(-1.0, std::min(1.0, c));
+            return std::acos(c);
+        };
+        for (size_t w = 0; w < np; ++w) P.dup[w] = angle(w, kpf) < 1e-3;
     }
     for (int K = 4; K <= kMaxK; ++K) {
         bool ok = true;
         for (size_t s = 0; s < sets.size() && ok; ++s) {
             const int m = ms[s];
-            const int kp = kprime_of(K, m), kpf = kprime_of(kMaxK, m);
+            const int kp = kprime_of(K, m);
             const auto &v = spec[s];
+            const Pre &P = pre[s];
             if (v.empty()) continue;
             double e = 0.0;
-            for (const auto &f : v) {
-                double a = 0.0;
-                for (int k = 1; k <= kp; ++k) a += f.re[k] * f.re[k] + f.im[k] * f.im[k];
-                e += 2.0 * a / ((double)m * m);
-            }
+            for (size_t w = 0; w < v.size(); ++w) e += 2.0 * P.e[w * (kMaxK + 1) + kp] / ((double)m * m);
             e /= (double)v.size();
             if (e < eta) { ok = false; break; }
             double coll = 0.0;
             int pairs = 0;
             for (size_t w = 0; w + 1 < v.size(); ++w) {
-                auto angle = [&](int kk) {
-                    double ab = 0.0, aa = 0.0, bb = 0.0;
-                    for (int k = 1; k <= kk; ++k) {
-                        ab += v[w].re[k] * v[w + 1].re[k] + v[w].im[k] * v[w + 1].im[k];
-                        aa += v[w].re[k] * v[w].re[k] + v[w].im[k] * v[w].im[k];
-                        bb += v[w + 1].re[k] * v[w + 1].re[k] + v[w + 1].im[k] * v[w + 1].im[k];
-                    }
-                    if (!(aa > 0.0 && bb > 0.0)) return 0.0;
+                if (P.dup[w]) continue;
+                const double ab = P.ab[w * (kMaxK + 1) + kp], aa = P.aa[w * (kMaxK + 1) + kp],
+                             bb = P.bb[w * (kMaxK + 1) + kp];
+                double th = 0.0;
+                if (aa > 0.0 && bb > 0.0) {
                     double c = ab / std::sqrt(aa * bb);
                     c = std::max(-1.0, std::min(1.0, c));
-                    return std::acos(c);
-                };
-                if (angle(kpf) < 1e-3) continue;
-                coll += std::pow(1.0 - angle(kp) / M_PI, (double)B);
+                    th = std::acos(c);
+                }
+                coll += std::pow(1.0 - th / M_PI, (double)B);
                 ++pairs;
             }
             if (pairs && (double)n * coll / pairs > 2.0 * gamma * alpha) ok = false;
@@ -694,10 +756,11 @@ static int run_pipeline(Run &R, Arena &ar) {
     // ---- per-request constants
     {
         std::vector<float> g((size_t)p.L * o.B * kFD);
-        for (int l = 0; l < p.L; ++l)
-            for (int bb = 0; bb < o.B; ++bb)
-                for (int c = 0; c < kFD; ++c)
-                    g[((size_t)l * o.B + bb) * kFD + c] = (float)gauss(o.seed, p.ms[l], bb, c);
+        std::vector<float> one((size_t)kMaxBits * kFD);
+        for (int l = 0; l < p.L; ++l) {
+            projections(o.seed, p.ms[l], one.data());
+            std::memcpy(g.data() + (size_t)l * o.B * kFD, one.data(), (size_t)o.B * kFD * sizeof(float));
+        }
         HIPCHK(hipMemcpyAsync(b.gproj, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
