@@ -586,7 +586,8 @@ __global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *_
 // length (blk_base), so the length's projections sit in LDS for all threads.
 namespace {
 struct KeysSmem {
-    float g[kMaxBits * kGLd];                 // SimHash projections of the length
+    uint16_t gh[32][32], gl[32][32];          // SimHash projections (bit x feature), bf16 hi, lo
+    float dots[kBlock / kWave][2][32][33];    // each wavefront's 64 x 32 projections
     double u[kJoinDirs][32];                  // the join's principal directions
 };
 
@@ -606,20 +607,29 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
     }
     const LenInfo L = q.len[l];
     const int tid = threadIdx.x;
-    for (int x = tid; x < q.B * kGLd; x += kBlock)
-        sm.g[x] = x % kGLd < kFD ? gproj[((int64_t)l * q.B + x / kGLd) * kFD + x % kGLd] : 0.0f;
+    for (int x = tid; x < 32 * 32; x += kBlock) {
+        const int bt = x / 32, c = x % 32;
+        const float gv = bt < q.B && c < kFD ? gproj[((int64_t)l * q.B + bt) * kFD + c] : 0.0f;
+        const uint32_t h = bf16_bits(gv);
+        sm.gh[bt][c] = (uint16_t)h;
+        sm.gl[bt][c] = (uint16_t)bf16_bits(gv - __uint_as_float(h << 16));
+    }
     if (q.udir)
         for (int x = tid; x < kJoinDirs * 32; x += kBlock)
             sm.u[x / 32][x % 32] = q.udir[(int64_t)l * kJoinDirs * 32 + x];
     __syncthreads();
     const int64_t j = ((int64_t)blockIdx.x - L.blk_base) * kBlock + tid;
-    if (j >= L.n_index) return;
-    const int64_t kk = L.kbase + j;
+    // every lane takes part in the wavefront's matrix products; lanes past
+    // the length's last window carry zeros and write nothing
+    const bool valid = j < L.n_index;
+    const int64_t kk = L.kbase + (valid ? j : 0);
 
     const FT *rec = (const FT *)q.F + kk * kRec;
     float f[kFD];
-    float erec, nrec;
-    if (sizeof(FT) == 8) {
+    float erec = 0.0f, nrec = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kFD; ++c) f[c] = 0.0f;
+    if (valid && sizeof(FT) == 8) {
 #pragma unroll
         for (int p = 0; p < kFD / 2; ++p) {
             const double2 v = *(const double2 *)(rec + 2 * p);
@@ -629,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
         const double2 v = *(const double2 *)(rec + kSlotErr);
         erec = (float)v.x;
         nrec = (float)(v.y * (1.0 + 1e-7));
-    } else {
+    } else if (valid) {
 #pragma unroll
         for (int p = 0; p < 7; ++p) {
             const float4 v = *(const float4 *)(rec + 4 * p);
@@ -645,45 +655,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
         nrec = v.w;
     }
 
-    // ---- SimHash bits: bit b = [<g_b, F> >= 0], most significant first;
-    // the margins |<g_b, F>| of the d prefix bits feed a sorted list of the
-    // kProbeSlots smallest (Hamming-1 probe order, Sec. 3.4 multi-probe).
-    // A list entry is the margin's bit pattern (ordered like the margin)
-    // with the bit index in its low five bits.
-    uint32_t sig = 0;
-    uint32_t top[kProbeSlots];
-#pragma unroll
-    for (int h = 0; h < kProbeSlots; ++h) top[h] = 0xFFFFFFFFu;
-#pragma unroll 1
-    for (int bt = 0; bt < q.B; ++bt) {
-        const float *gb = sm.g + bt * kGLd;
-        float dot = 0.0f;
-#pragma unroll
-        for (int c = 0; c < kFD; ++c) dot = fmaf(gb[c], f[c], dot);
-        if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
-        if (bt < L.depth) {
-            uint32_t v = (__float_as_uint(fabsf(dot)) & ~31u) | (uint32_t)bt;
-#pragma unroll
-            for (int h = 0; h < kProbeSlots; ++h) {
-                const uint32_t lo = min(top[h], v);
-                v = max(top[h], v);
-                top[h] = lo;
-            }
-        }
-    }
-    uint64_t order = 0;
-#pragma unroll
-    for (int h = 0; h < kProbeSlots; ++h)
-        if (h < L.probes) order |= (uint64_t)(top[h] & 31u) << (5 * h);
-    q.keyw[kk] = (uint64_t)sig | (order << 24);
-    const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
-    q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
-    q.sval[kk] = (uint32_t)kk;
-
-    // ---- join operands: G = hi + lo, hi = bf16(f), lo = bf16(f - hi); each
-    // component of G is within 2^-17 of the FP32 copy f (relative), and f is
-    // within u32 |F~| of the stored record F~, itself within e of F; so
-    // e' = e + (u32 + 2^-17) |F~| bounds |G - F|
+    // ---- the FP32 copy as bf16 pairs: G = hi + lo, hi = bf16(f),
+    // lo = bf16(f - hi); each component of G is within 2^-17 of f (relative)
     uint32_t hw[16], lw[16];
     double n2 = 0.0;
 #pragma unroll
@@ -704,13 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
         hw[w] = hp;
         lw[w] = lp;
     }
-    uint4 *jo = q.jop + kk * 8;
-#pragma unroll
-    for (int part = 0; part < 4; ++part) {
-        jo[part] = make_uint4(hw[4 * part], hw[4 * part + 1], hw[4 * part + 2], hw[4 * part + 3]);
-        jo[4 + part] = make_uint4(lw[4 * part], lw[4 * part + 1], lw[4 * part + 2], lw[4 * part + 3]);
-    }
-    // principal coordinates of the FP32 copy (FP64 dots), for the join's grid
+
+    // ---- principal coordinates of the FP32 copy (FP64 dots), for the
+    // join's grid (f is not needed past this point)
+    float pc0 = 0.0f, pc1 = 0.0f, pc2 = 0.0f;
     if (q.udir) {
         double p0 = 0.0, p1 = 0.0, p2 = 0.0;
 #pragma unroll
@@ -719,14 +689,114 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
             p1 = fma(sm.u[1][c], (double)f[c], p1);
             p2 = fma(sm.u[2][c], (double)f[c], p2);
         }
+        pc0 = (float)p0;
+        pc1 = (float)p1;
+        pc2 = (float)p2;
+    }
+
+    // ---- join operands (the bf16 pairs above; written first, so that only
+    // the pairs stay live through the matrix products): f is within u32 |F~|
+    // of the stored record F~, itself within e of F; so
+    // e' = e + (u32 + 2^-17) |F~| bounds |G - F|
+    if (valid) {
+        uint4 *jo = q.jop + kk * 8;
+#pragma unroll
+        for (int part = 0; part < 4; ++part) {
+            jo[part] = make_uint4(hw[4 * part], hw[4 * part + 1], hw[4 * part + 2], hw[4 * part + 3]);
+            jo[4 + part] = make_uint4(lw[4 * part], lw[4 * part + 1], lw[4 * part + 2], lw[4 * part + 3]);
+        }
         // w: the join's candidate Gram term 0.5 |G|^2, rounded down (its sign
         // bit is set per certify round by the grid keys)
-        q.gp[kk] = make_float4((float)p0, (float)p1, (float)p2,
-                               (float)(0.5 * (double)(float)n2 * (1.0 - 0x1.0p-23)));
+        if (q.udir)
+            q.gp[kk] = make_float4(pc0, pc1, pc2,
+                                   (float)(0.5 * (double)(float)n2 * (1.0 - 0x1.0p-23)));
+        const double ep =
+            ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
+        q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),
+                                  (float)((double)nrec * (1.0 + 0x1.0p-16)) * (1.0f + 2.4e-7f),
+                                  0.0f);
     }
-    const double ep = ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
-    q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),
-                              (float)((double)nrec * (1.0 + 0x1.0p-16)) * (1.0f + 2.4e-7f), 0.0f);
+
+    // ---- SimHash projections <g_b, G> of the wavefront's 64 windows on the
+    // matrix cores: two blocks of 32 windows x 32 bits (B used) over 32
+    // features (30 used), split bf16 (hi.hi + hi.lo + lo.hi, FP32 sums;
+    // within about 2^-16 |g| |f| of the FP32 dot, where bits near zero may
+    // flip -- keys steer candidates only, never validity).  Operand A of a
+    // block: lane L holds window (L mod 32) of the block and features
+    // 8 (L / 32) .. +8 of each 16-feature slice; a lane's other half comes
+    // from its partner L ^ 32.
+    const int lane = lane_id();
+    const int wv = tid / kWave;
+    const bool upper = lane >= 32;
+    const int col = lane & 31, koff = 8 * (lane >> 5);
+#pragma unroll 1
+    for (int bk = 0; bk < 2; ++bk) {
+        // block bk holds windows 32 bk .. 32 bk + 31: the lanes of that half
+        // own them, the other half holds their partners' features
+        const bool own = upper == (bk == 1);
+        mf32x16 c = {};
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            uint32_t ah[4], al[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t h0 = hw[8 * sl + i], h1 = hw[8 * sl + 4 + i];
+                const uint32_t l0 = lw[8 * sl + i], l1 = lw[8 * sl + 4 + i];
+                const uint32_t sh = (uint32_t)__shfl_xor((int)(upper ? h0 : h1), 32, kWave);
+                const uint32_t sl_ = (uint32_t)__shfl_xor((int)(upper ? l0 : l1), 32, kWave);
+                ah[i] = own ? (upper ? h1 : h0) : sh;
+                al[i] = own ? (upper ? l1 : l0) : sl_;
+            }
+            const mbf16x8 Ah = u4_as_bf16x8(make_uint4(ah[0], ah[1], ah[2], ah[3]));
+            const mbf16x8 Al = u4_as_bf16x8(make_uint4(al[0], al[1], al[2], al[3]));
+            const mbf16x8 bh = u4_as_bf16x8(*(const uint4 *)&sm.gh[col][16 * sl + koff]);
+            const mbf16x8 bl = u4_as_bf16x8(*(const uint4 *)&sm.gl[col][16 * sl + koff]);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, bl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, bh, c, 0, 0, 0);
+        }
+        // to LDS: register r of lane L is row 8 (r / 4) + 4 (L / 32) + r % 4,
+        // column L mod 32
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            sm.dots[wv][bk][8 * (r / 4) + 4 * (lane >> 5) + (r % 4)][col] = c[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (!valid) return;
+
+    // ---- SimHash bits: bit b = [<g_b, F> >= 0], most significant first;
+    // the margins |<g_b, F>| of the d prefix bits feed a sorted list of the
+    // kProbeSlots smallest (Hamming-1 probe order, Sec. 3.4 multi-probe).
+    // A list entry is the margin's bit pattern (ordered like the margin)
+    // with the bit index in its low five bits.
+    const float *mydots = sm.dots[wv][lane >> 5][lane & 31];
+    uint32_t sig = 0;
+    uint32_t top[kProbeSlots];
+#pragma unroll
+    for (int h = 0; h < kProbeSlots; ++h) top[h] = 0xFFFFFFFFu;
+#pragma unroll 1
+    for (int bt = 0; bt < q.B; ++bt) {
+        const float dot = mydots[bt];
+        if (dot >= 0.0f) sig |= 1u << (q.B - 1 - bt);
+        if (bt < L.depth) {
+            uint32_t v = (__float_as_uint(fabsf(dot)) & ~31u) | (uint32_t)bt;
+#pragma unroll
+            for (int h = 0; h < kProbeSlots; ++h) {
+                const uint32_t lo = min(top[h], v);
+                v = max(top[h], v);
+                top[h] = lo;
+            }
+        }
+    }
+    uint64_t order = 0;
+#pragma unroll
+    for (int h = 0; h < kProbeSlots; ++h)
+        if (h < L.probes) order |= (uint64_t)(top[h] & 31u) << (5 * h);
+    q.keyw[kk] = (uint64_t)sig | (order << 24);
+    const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
+    q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
+    q.sval[kk] = (uint32_t)kk;
 }
 
 // First slot of every bucket from the sorted keys: between two consecutive
