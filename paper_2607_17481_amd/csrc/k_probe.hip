@@ -22,9 +22,11 @@
 // order of Prop. 5).
 //
 // GPU mapping: one lane per query searches its candidates (lane-parallel
-// bound tests); the exact distances of the proposals (one per lane per round)
-// are computed kPerRound at a time by the lane groups of the wavefront, with
-// contiguous loads (group_zdist).
+// bound tests) until every lane still working holds a proposal; a lane that
+// holds one already (and whose own cell is finite) keeps searching for a
+// second meanwhile, so the wait for the slowest lane's search is used.  The
+// exact distances of the proposals are then computed for the whole
+// wavefront (verify_proposals), first slot, then second.
 //
 // One departure from the paper: a query stops once its own cell reaches 0
 // (the smallest possible value); the remaining candidates could only lower
@@ -112,19 +114,24 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
     int pr = -1, budget = q.budget_R;
     int64_t bs = 0, cut = 0, span = 0;
     int take = 0, rec = 0, str = 1, j = 0;
-    // current proposal
-    bool has = false;
-    uint32_t pc = 0;
-    int64_t pic = 0;
+    // current proposals (two slots)
+    bool has = false, has1 = false;
+    uint32_t pc = 0, pc1 = 0;
+    int64_t pic = 0, pic1 = 0;
     double pPc = 0.0, pmu = 0.0, pis = 0.0, plim = INFINITY;
+    double pPc1 = 0.0, pmu1 = 0.0, pis1 = 0.0, plim1 = INFINITY;
 
     for (;;) {
-        // ---- each lane advances to its next candidate that survives the prune
-        while (!done && !has) {
+        // ---- the wavefront searches until every lane still working holds a
+        // proposal; a lane that holds one already looks for a second meanwhile
+        while (__ballot(!done && !has) != 0) {
+            // a second proposal only once the query's own cell is finite
+            // (before that, its first distance often ends it: a repeat at 0)
+            if (done || has1 || (has && Pq == INFINITY)) continue;
             if (j >= take) {
                 // open the next bucket
                 ++pr;
-                if (pr > probes || budget <= 0) { done = true; break; }
+                if (pr > probes || budget <= 0) { done = true; continue; }
                 uint32_t b = prefix;
                 if (pr > 0) {
                     const int bit = (int)((kw >> (24 + 5 * (pr - 1))) & 31u);
@@ -163,15 +170,25 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
                 const float lb = lb_mem<FT>(fq, (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
                 if ((double)lb >= thr) continue;
             }
-            has = true;
-            plim = exit_bound(thr);
-            pc = kc;
-            pic = (int64_t)q.pcell[cs] - cell_base;
-            pPc = Pc;
-            pmu = q.mu[kc];
-            pis = q.isig[kc];
+            if (!has) {
+                has = true;
+                plim = exit_bound(thr);
+                pc = kc;
+                pic = (int64_t)q.pcell[cs] - cell_base;
+                pPc = Pc;
+                pmu = q.mu[kc];
+                pis = q.isig[kc];
+            } else {
+                has1 = true;
+                plim1 = exit_bound(thr);
+                pc1 = kc;
+                pic1 = (int64_t)q.pcell[cs] - cell_base;
+                pPc1 = Pc;
+                pmu1 = q.mu[kc];
+                pis1 = q.isig[kc];
+            }
         }
-        // ---- the wavefront verifies the proposals, four at a time
+        // ---- the wavefront verifies the first proposals
         const uint64_t mask = __ballot(has);
         if (mask == 0) break;
         auto on_result = [&](double dd) {
@@ -190,6 +207,27 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
         else
             verify_proposals(mask, SeriesA{q.t}, q.t, iq, muq, isq, pic, pmu, pis, m, on_result,
                              plim);
+        // the second slot (a lane whose own cell reached 0 drops it)
+        const uint64_t mask1 = __ballot(has1 && !done);
+        auto on_result1 = [&](double dd) {
+            ++n_ver;
+            const unsigned long long db = (unsigned long long)dbits(dd);
+            if (dd < Pq) {
+                atomicMin((unsigned long long *)&q.P[k], db);
+                Pq = dd;
+            }
+            if (dd < pPc1) atomicMin((unsigned long long *)&q.P[pc1], db);
+            if (Pq == 0.0) done = true;
+        };
+        if (mask1) {
+            if (staged)
+                verify_proposals(mask1, QwinA{qlo}, q.t, iq, muq, isq, pic1, pmu1, pis1, m, on_result1,
+                                 plim1);
+            else
+                verify_proposals(mask1, SeriesA{q.t}, q.t, iq, muq, isq, pic1, pmu1, pis1, m,
+                                 on_result1, plim1);
+        }
+        has1 = false;
     }
     // stats: one atomic per wave
     unsigned long long a = n_cand, v = n_ver;
