@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kWave) void k_pca(const double *__restrict__ cov, i
 // has one coordinate only, in finer cells (a band), for radii below the
 // resolution of the two-coordinate grid.
 __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__restrict__ gl,
-                                                      int64_t N, int cb1, int cb2,
+                                                      int64_t N, int cb1, int cb2, int cb3,
                                                       uint32_t *__restrict__ gkey,
                                                       uint32_t *__restrict__ gval,
                                                       uint8_t *__restrict__ qf,
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
     const int l = find_len_k_wave(q.len, q.L, k_first, k);
     const GridLen &G = gl[l];
     const float4 c = gp[k];
-    const double p1 = c.x, p2 = c.y;
+    const double p1 = c.x, p2 = c.y, p3 = c.z;
     auto cell = [&](double p, int bits) -> uint32_t {
         const uint32_t top = (1u << bits) - 1u;
         const double x = (p - G.qlo) * G.hinv;
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
         if (x >= (double)top) return top;
         return (uint32_t)x;
     };
-    gkey[k] = ((uint32_t)l << (cb1 + cb2)) | (cell(p1, cb1) << cb2) | (cb2 ? cell(p2, cb2) : 0u);
+    gkey[k] = ((uint32_t)l << (cb1 + cb2 + cb3)) | (cell(p1, cb1) << (cb2 + cb3)) |
+              (cb2 ? cell(p2, cb2) << cb3 : 0u) | (cb3 ? cell(p3, cb3) : 0u);
     gval[k] = (uint32_t)k;
     const bool f = q.P[k] != 0ull;
     qf[k] = f;
@@ -347,7 +348,7 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
                                                        const uint4 *__restrict__ jop,
                                                        const float4 *__restrict__ jmeta,
                                                        const float4 *__restrict__ gp,
-                                                       int64_t ntiles, int cb1, int cb2,
+                                                       int64_t ntiles, int cb1, int cb2, int cb3,
                                                        double T) {
     __shared__ uint2 queue[kJoinWaves][kQueueCap];
     __shared__ float roww[kJoinWaves][kJT];           // the queries' Gram filter terms
@@ -403,11 +404,12 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
     __builtin_amdgcn_wave_barrier();
 
     // ---- the rows of adjacent cells
-    const uint32_t mask1 = (1u << cb1) - 1u, mask2 = (1u << cb2) - 1u;
+    const uint32_t mask1 = (1u << cb1) - 1u, mask2 = (1u << cb2) - 1u, mask3 = (1u << cb3) - 1u;
     const uint32_t key_q = validq ? gkey[pq] : 0u;
-    const int c1q = (int)((key_q >> cb2) & mask1), c2q = (int)(key_q & mask2);
+    const int c1q = (int)((key_q >> (cb2 + cb3)) & mask1), c2q = (int)((key_q >> cb3) & mask2);
+    const int c3q = (int)(key_q & mask3);
     const int c1min = wave_min_i(isq ? c1q : INT_MAX), c1max = wave_max_i(isq ? c1q : -1);
-    const uint32_t lbits = (uint32_t)l << (cb1 + cb2);
+    const uint32_t lbits = (uint32_t)l << (cb1 + cb2 + cb3);
     unsigned long long n_pairs = 0, n_kept = 0, n_ver = 0;
     int qn = 0;                                           // queued pairs (uniform)
 
@@ -433,10 +435,32 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
     int c1p = max(c1min - 1, 0) - 1;
     const int c1end = min(c1max + 1, (int)mask1);
     int64_t c0 = 0, cend = 0;
+    int c2p = 0, c2end = -1;                              // three coordinates: the row's c2 range
     // move [c0, cend) to the next non-empty run once the current one is used
     // up (uniform); false when there is none
     auto next_run = [&]() -> bool {
-        if (cb2 == 0) {
+        if (cb3 > 0) {
+            // three coordinates: one run per pair of adjacent (c1, c2) cells,
+            // over the c3 cells next to the queries of that pair
+            while (c0 >= cend && (c2p < c2end || c1p < c1end)) {
+                if (c2p >= c2end) {
+                    ++c1p;
+                    const bool near1 = isq && abs(c1q - c1p) <= 1;
+                    if (__ballot(near1) == 0) continue;
+                    c2p = wave_min_i(near1 ? max(c2q - 1, 0) : INT_MAX) - 1;
+                    c2end = wave_max_i(near1 ? min(c2q + 1, (int)mask2) : -1);
+                    continue;
+                }
+                ++c2p;
+                const bool near = isq && abs(c1q - c1p) <= 1 && abs(c2q - c2p) <= 1;
+                if (__ballot(near) == 0) continue;
+                const int c3lo = wave_min_i(near ? max(c3q - 1, 0) : INT_MAX);
+                const int c3hi = wave_max_i(near ? min(c3q + 1, (int)mask3) : -1);
+                const uint32_t rk = lbits | ((uint32_t)c1p << (cb2 + cb3)) | ((uint32_t)c2p << cb3);
+                c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c3lo);
+                cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c3hi) + 1u);
+            }
+        } else if (cb2 == 0) {
             // one coordinate: the cells next to the queries' cells form a
             // single run of the order
             if (c0 >= cend && c1p < c1end) {
@@ -570,26 +594,27 @@ void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hi
     hipLaunchKernelGGL(k_pca, dim3((unsigned)q.L), dim3(kWave), 0, s, cov, q.L, udir);
 }
 
-void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2,
+void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2, int cb3,
                       uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
                       hipStream_t s) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1, cb2, gkey,
-                       gval, qf, gp);
+    hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1, cb2, cb3,
+                       gkey, gval, qf, gp);
 }
 
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
                        const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
+                       int cb3,
                        double T, hipStream_t s) {
     if (ntiles <= 0) return;
     const unsigned nb = (unsigned)((ntiles + kJoinWaves - 1) / kJoinWaves);
     if (precision == 0)
         hipLaunchKernelGGL(k_join_tiles<double>, dim3(nb), dim3(kJoinWaves * kWave), 0, s, q, gl,
-                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
+                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, cb3, T);
     else
         hipLaunchKernelGGL(k_join_tiles<float>, dim3(nb), dim3(kJoinWaves * kWave), 0, s, q, gl,
-                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, T);
+                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, cb3, T);
 }
 
 }  // namespace pmp

@@ -446,13 +446,14 @@ void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t n
 size_t join_cov_doubles(int L);
 // principal directions: covariance of a sample, then power iteration (GPU)
 void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s);
-void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2,
+// grid keys over cb1 (and cb2, cb3 when nonzero) bits of the principal coordinates
+void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2, int cb3,
                       uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
                       hipStream_t s);
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
                        const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
-                       double T, hipStream_t s);
+                       int cb3, double T, hipStream_t s);
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);

@@ -854,8 +854,12 @@ static int run_pipeline(Run &R, Arena &ar) {
             gl[l].tile_base = ntiles;
             ntiles += (p.len[l].n_index + kJoinTile - 1) / kJoinTile;
         }
-        // two grid coordinates of cb bits each, or, when some length's radius
-        // is below that grid's resolution, one coordinate of cb1 bits
+        // three grid coordinates of cb3d bits each or two of cb bits, as far
+        // as every length's radius resolves at that grid's cell width; else
+        // one coordinate of cb_fine bits.  Each further coordinate cuts the
+        // pairs the tiles form (at ECG-like data the third keeps about a
+        // quarter of the pairs the first two let through)
+        const int cb3d = std::min(8, (31 - p.len_bits) / 3);
         const int cb = std::min(10, (31 - p.len_bits) / 2);
         const int cb_fine = 31 - p.len_bits;
         for (;;) {
@@ -864,7 +868,7 @@ static int run_pipeline(Run &R, Arena &ar) {
             // R: radius on the join vectors G (bf16 pairs); Rf: on the FP32
             // feature copies f, which place the grid
             std::vector<double> Rl(p.L), Rf(p.L);
-            bool two_d = true;
+            bool two_d = true, three_d = true;
             for (int l = 0; l < p.L; ++l) {
                 const double m = p.ms[l];
                 const double nmax = m / std::sqrt(2.0) * 1.01 + 1.0;
@@ -877,8 +881,12 @@ static int run_pipeline(Run &R, Arena &ar) {
                 Rf[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * efmax;
                 if (p.len[l].n_index > 0 && Rf[l] * (double)(1u << cb) < 2.0 * (nmax * 1.001 + 1e-9))
                     two_d = false;
+                if (p.len[l].n_index > 0 && Rf[l] * (double)(1u << cb3d) < 2.0 * (nmax * 1.001 + 1e-9))
+                    three_d = false;
             }
-            const int cb1 = two_d ? cb : cb_fine, cb2 = two_d ? cb : 0;
+            const int cb1 = three_d ? cb3d : two_d ? cb : cb_fine;
+            const int cb2 = three_d ? cb3d : two_d ? cb : 0;
+            const int cb3 = three_d ? cb3d : 0;
             for (int l = 0; l < p.L; ++l) {
                 const double m = p.ms[l];
                 const double nmax = m / std::sqrt(2.0) * 1.01 + 1.0;
@@ -904,10 +912,11 @@ static int run_pipeline(Run &R, Arena &ar) {
                 G.sqrt2m = (float)std::sqrt(2.0 / m) * (1.0f + 1e-7f);
             }
             HIPCHK(hipMemcpyAsync(b.gl, gl.data(), p.L * sizeof(GridLen), hipMemcpyHostToDevice, s));
-            launch_grid_keys(q, b.gl, N, cb1, cb2, b.jk, b.jv, b.qf, b.gp, s);
-            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + cb1 + cb2, b.sort_tmp, s);
+            launch_grid_keys(q, b.gl, N, cb1, cb2, cb3, b.jk, b.jv, b.qf, b.gp, s);
+            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + cb1 + cb2 + cb3, b.sort_tmp,
+                             s);
             launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntiles,
-                              cb1, cb2, Teff, s);
+                              cb1, cb2, cb3, Teff, s);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(s));   // gl is rewritten next round
             rc = select_topk(p, b, R.k, s, acc);
