@@ -251,15 +251,15 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
     const GridLen &G = gl[l];
     const float4 c = gp[k];
     const double p1 = c.x, p2 = c.y, p3 = c.z;
-    auto cell = [&](double p, int bits) -> uint32_t {
+    auto cell = [&](double p, int bits, double hinv) -> uint32_t {
         const uint32_t top = (1u << bits) - 1u;
-        const double x = (p - G.qlo) * G.hinv;
+        const double x = (p - G.qlo) * hinv;
         if (!(x > 0.0)) return 0u;
         if (x >= (double)top) return top;
         return (uint32_t)x;
     };
-    gkey[k] = ((uint32_t)l << (cb1 + cb2 + cb3)) | (cell(p1, cb1) << (cb2 + cb3)) |
-              (cb2 ? cell(p2, cb2) << cb3 : 0u) | (cb3 ? cell(p3, cb3) : 0u);
+    gkey[k] = ((uint32_t)l << (cb1 + cb2 + cb3)) | (cell(p1, cb1, G.hinv) << (cb2 + cb3)) |
+              (cb2 ? cell(p2, cb2, G.hinv2) << cb3 : 0u) | (cb3 ? cell(p3, cb3, G.hinv2) : 0u);
     gval[k] = (uint32_t)k;
     const bool f = q.P[k] != 0ull;
     qf[k] = f;

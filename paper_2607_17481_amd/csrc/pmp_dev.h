@@ -139,7 +139,8 @@ constexpr int kJoinDirs = 3;              // principal directions per length in 
 struct GridLen {
     int64_t tile_base;    // first join tile of this length
     double qlo;           // grid origin of both coordinates
-    double hinv;          // 1 / cell width (0: one cell)
+    double hinv;          // 1 / cell width of the first coordinate (0: one cell)
+    double hinv2;         // 1 / cell width of the second and third coordinates
     double R2;            // squared radius on the join vectors G (+inf: every pair)
     double eps_c;         // MFMA dot-product error per unit |G_q| (times the largest |G_c|)
     double nmax2;         // square of the largest |G|

@@ -892,16 +892,20 @@ static int run_pipeline(Run &R, Arena &ar) {
                 const double nmax = m / std::sqrt(2.0) * 1.01 + 1.0;
                 GridLen &G = gl[l];
                 G.qlo = -(nmax * 1.001 + 1e-9);
+                // each coordinate's cells span [qlo, -qlo] in 2^bits cells at
+                // least as wide as the radius
                 const double hmin = 2.0 * -G.qlo / (double)(1u << cb1) * (1.0 + 1e-9);
+                const double hmin2 = 2.0 * -G.qlo / (double)(1u << std::max(cb2, 1)) * (1.0 + 1e-9);
                 if (std::isinf(Rl[l])) {
                     G.R2 = INFINITY;
-                    G.hinv = 0.0;
+                    G.hinv = G.hinv2 = 0.0;
                 } else {
                     G.R2 = Rl[l] * Rl[l] * (1.0 + 1e-9);
                     // coordinates are computed in FP64 from floats: 1e-12 nmax
                     // covers their rounding
-                    const double h = std::max((Rf[l] * (1.0 + 1e-9) + 1e-12 * nmax) * (1.0 + 1e-9), hmin);
-                    G.hinv = 1.0 / h;
+                    const double hr = (Rf[l] * (1.0 + 1e-9) + 1e-12 * nmax) * (1.0 + 1e-9);
+                    G.hinv = 1.0 / std::max(hr, hmin);
+                    G.hinv2 = 1.0 / std::max(hr, hmin2);
                 }
                 G.eps_c = 1.6e-5 * nmax;
                 // per-pair test on the stored coordinates (floats, each within
