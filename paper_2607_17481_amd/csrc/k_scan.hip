@@ -2,8 +2,10 @@
 //
 // The radix sort ranks keys inside a wave with ballots (one ballot per digit
 // bit gives each lane the set of lanes holding the same digit), so a block
-// needs no LDS histogram per thread; waves are chained through small LDS
-// tables and blocks through a scan of per-(digit, block) counts.  Stability
+// needs no LDS histogram per thread; each wave takes a contiguous slice of
+// its block's tile, waves are chained through a small LDS table of digit
+// counts (one block barrier), and blocks through a scan of per-(digit,
+// block) counts.  Stability
 // (equal keys keep their input order) is what keeps each bucket of the
 // directory sorted by window start.
 #include "pmp_dev.h"
@@ -139,47 +141,74 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t *__restric
     counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// One tile of kSortTile keys per block; wavefront w takes the contiguous
+// slice [w, w + 1) * kSortTile / 4 in kSortRounds rounds of 64.  Pass 1 ranks
+// each key among the equal digits of its round (one ballot per digit bit) and
+// counts each wavefront's digits; after one block barrier every (wavefront,
+// digit) knows its first output position (the block's offset of the digit
+// plus the counts of the earlier wavefronts); pass 2 writes the keys with no
+// further barrier.  Stable: within a digit, wavefronts, rounds and lanes keep
+// their input order.
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift, int nbits,
     const uint32_t *__restrict__ offs, int64_t nblocks) {
-    __shared__ uint32_t running[kRadix];
-    __shared__ uint32_t wcnt[kBlock / kWave][kRadix];
+    constexpr int kW = kBlock / kWave;
+    __shared__ uint32_t wcnt[kW][kRadix];
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
     const uint32_t mask = (1u << nbits) - 1u;
-    running[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int q = 0; q < kW; ++q) wcnt[q][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / kW);
+    uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        for (int q = 0; q < kBlock / kWave; ++q) wcnt[q][threadIdx.x] = 0;
-        __syncthreads();
-        int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        const int64_t i = base + (int64_t)r * kWave + lane;
         const bool valid = i < n;
-        uint32_t key = valid ? kin[i] : 0u;
-        uint32_t val = valid ? vin[i] : 0u;
-        uint32_t dig = (key >> shift) & mask;
-        // lanes of this wave holding the same digit
+        key[r] = valid ? kin[i] : 0u;
+        val[r] = valid ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + (int64_t)r * kWave + lane;
+        const bool valid = i < n;
+        const uint32_t dig = (key[r] >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
-            uint64_t bal = __ballot((dig >> b) & 1u);
+            const uint64_t bal = __ballot((dig >> b) & 1u);
             peers &= ((dig >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t rank = __popcll(peers & lanemask_lt());
-        if (valid && rank == 0) wcnt[w][dig] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = running[dig] + rank;
-            for (int q = 0; q < w; ++q) pos += wcnt[q][dig];
-            kout[pos] = key;
-            vout[pos] = val;
+        const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
+        // the digit's count so far in this wavefront (earlier rounds) plus the
+        // equal digits of earlier lanes; the leader then adds the round's count
+        rank[r] = below + (valid ? wcnt[w][dig] : 0u);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) wcnt[w][dig] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        // thread d: the first position of digit d for each wavefront
+        const int d = threadIdx.x;
+        uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+        for (int q = 0; q < kW; ++q) {
+            const uint32_t c = wcnt[q][d];
+            wcnt[q][d] = run;
+            run += c;
         }
-        __syncthreads();
-        {
-            uint32_t add = 0;
-            for (int q = 0; q < kBlock / kWave; ++q) add += wcnt[q][threadIdx.x];
-            running[threadIdx.x] += add;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + (int64_t)r * kWave + lane;
+        if (i < n) {
+            const uint32_t pos = wcnt[w][(key[r] >> shift) & mask] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
         }
-        __syncthreads();
     }
 }
 
