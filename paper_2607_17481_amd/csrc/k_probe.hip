@@ -59,7 +59,6 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
     const int64_t k_first = (int64_t)blockIdx.x * kWave;
     const int64_t k = k_first + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
-    int64_t s = 0;
 
     // ---- per-lane query state
     bool done = k >= N;
@@ -82,7 +81,6 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
         bb = bstart + L.bucket_base;
         sqrt2m = (float)sqrt(2.0 / (double)m) * (1.0f + 1e-7f);
         cq = q.cell[k];
-        s = q.inv[k];
         iq = (int64_t)cq - cell_base;
         kw = q.keyw[k];
         prefix = d ? (uint32_t)(kw & 0xFFFFFFu) >> (q.B - d) : 0u;
@@ -138,9 +136,10 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
                     b = prefix ^ (1u << (d - 1 - bit));
                 }
                 bs = bb[b];
-                // the valid entries (cell <= lim) form a prefix of the bucket;
-                // in the own bucket they all lie before the query's slot s
-                int64_t lo = bs, hi = pr == 0 ? s : (int64_t)bb[b + 1];
+                // the valid entries (cell <= lim) form a prefix of the bucket
+                // (in the own bucket the query and everything after it lie
+                // past the prefix)
+                int64_t lo = bs, hi = (int64_t)bb[b + 1];
                 while (lo < hi) {
                     const int64_t mid = (lo + hi) >> 1;
                     if (q.pcell[mid] <= lim) lo = mid + 1; else hi = mid;

@@ -818,19 +818,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_bounds(Req q, int64_t N, int6
     for (int64_t b = prev + 1; b <= cur; ++b) bstart[b] = (uint32_t)s;
 }
 
-// Slot maps after the sort: k -> slot and slot -> cell.
+// Slot map after the sort: slot -> cell.
 __global__ __launch_bounds__(kBlock) void k_slot_maps(Req q, int64_t N) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= N) return;
-    const uint32_t k = q.perm[s];
-    q.inv[k] = (uint32_t)s;
-    q.pcell[s] = q.cell[k];
-}
-
-__global__ __launch_bounds__(kBlock) void k_invert(const uint32_t *__restrict__ perm, int64_t N,
-                                                   uint32_t *__restrict__ inv) {
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s < N) inv[perm[s]] = (uint32_t)s;
+    q.pcell[s] = q.cell[q.perm[s]];
 }
 
 // ------------------------------------------------------------ launchers
@@ -906,8 +898,5 @@ void launch_slot_maps(const Req &q, int64_t N, hipStream_t s) {
     if (N > 0) hipLaunchKernelGGL(k_slot_maps, dim3(nblk(N)), dim3(kBlock), 0, s, q, N);
 }
 
-void launch_invert(const uint32_t *perm, int64_t N, uint32_t *inv, hipStream_t s) {
-    if (N > 0) hipLaunchKernelGGL(k_invert, dim3(nblk(N)), dim3(kBlock), 0, s, perm, N, inv);
-}
 
 }  // namespace pmp

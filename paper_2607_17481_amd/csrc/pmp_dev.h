@@ -72,7 +72,6 @@ struct Req {
     uint32_t *sval;        // [N] sort values (k)
     uint32_t *perm;        // [N] slot -> k
     uint32_t *pcell;       // [N] slot -> cell
-    uint32_t *inv;         // [N] k -> slot
     const float *gproj;    // [L][B][30] SimHash projections
     float   *emax;         // [L] largest e_i of each length
     unsigned long long *counters;   // stats counters
@@ -428,7 +427,6 @@ void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const ui
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);
-void launch_invert(const uint32_t *perm, int64_t N, uint32_t *inv, hipStream_t s);
 // (k_probe.hip)
 void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, int max_m,
                   hipStream_t s);

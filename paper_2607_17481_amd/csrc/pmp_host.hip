@@ -397,7 +397,7 @@ struct Bufs {
     float4 *jmeta;
     uint8_t *qf;
     float4 *gp;
-    uint32_t *skey, *sval, *skey2, *sval2, *pcell, *inv, *bstart;
+    uint32_t *skey, *sval, *skey2, *sval2, *pcell, *bstart;
     void *sort_tmp;
     uint32_t *jk, *jv, *jk2, *jv2;
     uint32_t *sel_cnt, *less_k, *eq_k, *sel_cell;
@@ -454,7 +454,6 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
     b.skey2 = take<uint32_t>(a, N);
     b.sval2 = take<uint32_t>(a, N);
     b.pcell = take<uint32_t>(a, N);
-    b.inv = take<uint32_t>(a, N);
     b.bstart = take<uint32_t>(a, p.nbuckets + 1);
     b.sort_tmp = a.take(sort_temp_bytes(N));
     b.jk = take<uint32_t>(a, N);
@@ -794,7 +793,6 @@ static int run_pipeline(Run &R, Arena &ar) {
     q.sval = b.sval;
     q.perm = b.sval;
     q.pcell = b.pcell;
-    q.inv = b.inv;
     q.gproj = b.gproj;
     q.emax = b.emax;
     q.counters = b.counters;
