@@ -166,22 +166,31 @@ __device__ __forceinline__ void sketch_record(const Req &q, int m, int kprime,
 // windows 4 tid .. 4 tid + 3; a block scan) and the list of those windows,
 // then their two-pass moments (Sec. 3.2), dealt evenly over the threads from
 // the list, with their cell and the initial profile value.  Ends with the
-// block synchronized and kpos final.
+// block synchronized and kpos final (and, when given, smu / sis: the mean
+// and 1 / sigma of each non-constant window by its place in the tile).
 __device__ __forceinline__ void tile_positions_and_moments(
     const Req &q, const LenInfo &L, int64_t i0, int nw, int64_t tile, const double *st,
     const uint32_t *__restrict__ E, const uint32_t *__restrict__ tile_off, int32_t *kpos,
-    uint16_t *widx, uint32_t *wsum) {
+    uint16_t *widx, uint32_t *wsum, double *smu = nullptr, double *sis = nullptr) {
     const int m = L.m;
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wv = tid / kWave;
     {
+        // the eight change-point counts are loaded together (indices
+        // clamped to the tile's last window, which stays within E[0..n])
+        uint32_t ea[4], eb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t w = i0 + min(4 * tid + j, nw - 1);
+            ea[j] = E[w + m];
+            eb[j] = E[w + 1];
+        }
         bool ix[4];
         int c = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int w = 4 * tid + j;
-            ix[j] = w < nw && E[i0 + w + m] != E[i0 + w + 1];
+            ix[j] = 4 * tid + j < nw && ea[j] != eb[j];
             c += ix[j];
         }
         int x = c;                                               // inclusive wave scan
@@ -250,6 +259,10 @@ __device__ __forceinline__ void tile_positions_and_moments(
         q.mu[kk] = mu;
         q.isig[kk] = is;
         q.P[kk] = kInfBits;
+        if (smu) {
+            smu[w] = mu;
+            sis[w] = is;
+        }
     }
     __syncthreads();
 }
@@ -421,17 +434,22 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
 //   X[w][f] = sum_r y_w[r] B[r][f],   y_w = t[w + .] - mu_w (by Lemma 1 the
 //   shift leaves every bin k >= 1 unchanged),
 //   B[r][2k-2] = cos(2 pi k r / m),  B[r][2k-1] = -sin(2 pi k r / m),
-// done on the matrix cores with FP32 accumulation: form 1 splits y and B
-// into bf16 pairs (hi + lo) and sums hi.hi + hi.lo + lo.hi (FP32-grade
-// results), form 2 uses one bf16 product.  Each window's record carries the
-// derived bound e_i on its error, so the Parseval prune stays a true lower
-// bound; moments stay FP64 (shared with the FP64 form).
+// done on the matrix cores with FP32 accumulation.  Form 1 splits the
+// float values of y and B exactly into three bf16 parts each (hi + mid +
+// lo) and keeps the six products of weight 2^-16 and above (hi.hi in an
+// accumulator of its own, the other five in a second); only mid.lo, lo.mid
+// and lo.lo (below 2^-23 of each product) are dropped, so the results are
+// FP32-grade.  Form 2 uses one bf16 product.  Each window's record carries
+// the derived bound e_i on its error, so the Parseval prune stays a true
+// lower bound; moments stay FP64 (shared with the FP64 form).
 
-// Basis in bf16 pairs, per length: [f (32)][r (m rounded up to 16)], hi
-// then lo.  Computed in FP64 from the exact phase (k r mod m) / m.
+// Basis as float values split into three bf16 parts, per length: [f (32)][r
+// (m rounded up to 16)], one table per part.  Computed in FP64 from the
+// exact phase (k r mod m) / m.
 __global__ __launch_bounds__(kBlock) void k_basis(const LenInfo *__restrict__ len, int L,
                                                   const int64_t *__restrict__ base,
                                                   uint16_t *__restrict__ bh,
+                                                  uint16_t *__restrict__ bm,
                                                   uint16_t *__restrict__ bl) {
     const int l = blockIdx.y;
     if (l >= L) return;
@@ -449,8 +467,11 @@ __global__ __launch_bounds__(kBlock) void k_basis(const LenInfo *__restrict__ le
         }
         const float vf = (float)v;
         const uint32_t h = bf16_bits(vf);
+        const float r1 = vf - __uint_as_float(h << 16);   // exact
+        const uint32_t md = bf16_bits(r1);
         bh[o + x] = (uint16_t)h;
-        bl[o + x] = (uint16_t)bf16_bits(vf - __uint_as_float(h << 16));
+        bm[o + x] = (uint16_t)md;
+        bl[o + x] = (uint16_t)bf16_bits(r1 - __uint_as_float(md << 16));   // exact
     }
 }
 
@@ -470,15 +491,17 @@ __device__ __forceinline__ mbf16x8 u4_as_bf16x8(uint4 v) {
 }  // namespace
 
 template <int kProducts>
-__global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *__restrict__ E,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch_mfma(Req q, const uint32_t *__restrict__ E,
                                                         const uint32_t *__restrict__ tile_off,
                                                         const int64_t *__restrict__ bbase,
                                                         const uint16_t *__restrict__ bh,
+                                                        const uint16_t *__restrict__ bm,
                                                         const uint16_t *__restrict__ bl) {
     extern __shared__ double dyn[];
     __shared__ int32_t kpos[kTileW];
     __shared__ uint16_t widx[kTileW];
     __shared__ uint32_t wsum[kBlock / kWave];
+    __shared__ double smu[kTileW], sis[kTileW];
     __shared__ int emax_s;
     const int64_t tile = blockIdx.x;
     const int l = find_tile_len(q.len, q.L, tile);
@@ -494,78 +517,145 @@ __global__ __launch_bounds__(kBlock) void k_sketch_mfma(Req q, const uint32_t *_
 
     if (tid == 0) emax_s = 0;
     for (int r = tid; r < nw + mp + kMBlk; r += kBlock) st[r] = r < nw + m - 1 ? q.t[i0 + r] : 0.0;
-    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, widx, wsum);
+    tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, widx, wsum, smu, sis);
 
     const uint4 *Bh = (const uint4 *)(bh + bbase[l]);
+    const uint4 *Bm = (const uint4 *)(bm + bbase[l]);
     const uint4 *Bl = (const uint4 *)(bl + bbase[l]);
     const int i = lane % kMBlk, hh = lane / kMBlk;
     const double u64 = 1.1102230246251565e-16;
-    // Each window is centred on its own mean, y = t - mu, so that
-    // sum_r |y_r| <= m sigma.  Per component, relative to sum |y_r| |B|:
-    // the float and bf16 roundings of y and B (and the dropped lo.lo), and
-    // the FP32 sums of each 16-sample chunk (3 x 16 products from zero,
-    // rounding up to 2^-23); chunks add up in FP64.
-    const double per = (kProducts == 3 ? 3.1 * 0x1.0p-18 : 2.01 * 0x1.0p-9) + 0x1.0p-24 +
-                       (kProducts * 16) * 0x1.0p-23 * 1.01 + 1e-15;
-    const double ecomp = sqrt(2.0 * L.kprime) * per * (double)m * (1.0 + 1e-6);
+    // Error bound.  Each window is centred on its own mean, y = t - mu, so
+    // |y|^2 = m sigma^2.  Every rounding of a component (basis row B, the
+    // cos or sin of one bin) is below per * sum_r |y_r| |B_r|, and over the
+    // 2K' rows sum (sum_r |y_r||B_r|)^2 <= |y|^2 sum_rows |B_row|^2 = m
+    // sigma^2 K' m, since cos^2 + sin^2 = 1 at every sample (Cauchy-Schwarz).
+    // The feature vector X / sigma is therefore within sqrt(K') m per.
+    // per: y and B rounded to float (2 x 2^-24) and the FP64 centring and
+    // chunk sums ((m / 8 + 4) u64); then, with u = 2^-8 the bf16 unit
+    // roundoff and every FP32 addition rounding by up to 2^-23,
+    //   form 1: mid.lo + lo.mid + lo.lo <= (2 (1 + u) u^3 + u^4) < 2^-23
+    //     (|mid| <= (1 + u) u |y|, |lo| <= u^2 |y|); hi.hi summed from zero
+    //     per chunk of 16 samples (16 additions over products within (1 +
+    //     u)^2 of |y_r B_r|); the other five products, together below 1.03
+    //     x 2^-7 of |y_r B_r|, summed from zero over groups of 4 chunks
+    //     (320 additions);
+    //   form 2: the bf16 roundings of y and B, u + (1 + u) u = 2u + u^2,
+    //     and 16 additions.
+    // The float and bf16 values of normal-range samples are exact splits;
+    // flushed subnormals (the parts, products and partial sums of one
+    // sample, at most 16 of them) add at most 2^-122 per sample in absolute
+    // terms, counted separately below.
+    const double per = 2.0 * 0x1.0p-24 + ((double)m / 8.0 + 4.0) * u64 +
+                       (kProducts == 6 ? 0x1.0p-23 * 1.01 + 16.0 * 0x1.0p-23 * 1.01 +
+                                             320.0 * 0x1.0p-23 * 1.03 * 0x1.0p-7 * 1.01
+                                       : (2.0 * 0x1.0p-8 + 0x1.0p-16) * 1.01 +
+                                             16.0 * 0x1.0p-23 * 1.02);
+    const double ecomp = sqrt((double)L.kprime) * per * (double)m * (1.0 + 1e-6);
+    const double eabs = sqrt(2.0 * L.kprime) * (double)m * 0x1.0p-122;
     float emax = 0.0f;
     for (int blk = wv; blk < kTileW / kMBlk; blk += kBlock / kWave) {
         const int w0 = blk * kMBlk;
         if (w0 >= nw) break;
         const int32_t kw = i < nw - w0 ? kpos[w0 + i] : -1;
         if (__ballot(kw >= 0) == 0) continue;
-        const double mu = kw >= 0 ? q.mu[kw] : 0.0;
+        const double mu = kw >= 0 ? smu[w0 + i] : 0.0;
         const double *x = st + w0 + i + 8 * hh;      // window i, this lane's half of each chunk
 
         double sum[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v) sum[v] = 0.0;
+        mf32x16 acc2 = {};
+        // B operands of feature i, samples r0 + 8 hh .. + 7: loaded one chunk
+        // ahead
+        int bo = (i * mp + 8 * hh) / 8;
+        uint4 nbh = Bh[bo], nbm = nbh, nbl = nbh;
+        if (kProducts == 6) {
+            nbm = Bm[bo];
+            nbl = Bl[bo];
+        }
         for (int r0 = 0; r0 < mp; r0 += 16) {
-            // A: window i, samples r0 + 8 hh .. + 7 (centred, split);  B:
-            // feature i, the same samples
-            mbf16x8 ah, al;
+            const mbf16x8 bhv = u4_as_bf16x8(nbh);
+            const mbf16x8 bmv = u4_as_bf16x8(nbm), blv = u4_as_bf16x8(nbl);
+            if (r0 + 16 < mp) {
+                bo += 2;
+                nbh = Bh[bo];
+                if (kProducts == 6) {
+                    nbm = Bm[bo];
+                    nbl = Bl[bo];
+                }
+            }
+            // A: window i, the same samples (centred, split by the
+            // hardware's round-to-nearest-even conversion of the float
+            // value; the empty asm keeps the compiler from rounding the
+            // FP64 difference to bf16 directly, which gives the same bits
+            // through a longer sequence)
+            float yf[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float yf = (float)(x[r0 + e] - mu);
-                const uint32_t h = bf16_bits(yf);
-                ah[e] = __builtin_bit_cast(__bf16, (uint16_t)h);
-                if (kProducts == 3)
-                    al[e] = __builtin_bit_cast(
-                        __bf16, (uint16_t)bf16_bits(yf - __uint_as_float(h << 16)));
+                yf[e] = (float)(x[r0 + e] - mu);
+                asm("" : "+v"(yf[e]));
             }
-            const int bo = (i * mp + r0 + 8 * hh) / 8;
-            const mbf16x8 bhv = u4_as_bf16x8(Bh[bo]);
+            mbf16x8 ah, am, al;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ah[e] = (__bf16)yf[e];
+            if (kProducts == 6) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    yf[e] -= (float)ah[e];                                // exact
+                    am[e] = (__bf16)yf[e];
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) al[e] = (__bf16)(yf[e] - (float)am[e]);   // exact
+            }
             mf32x16 acc = {};
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhv, acc, 0, 0, 0);
-            if (kProducts == 3) {
-                const mbf16x8 blv = u4_as_bf16x8(Bl[bo]);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc, 0, 0, 0);
+            if (kProducts == 6) {
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bmv, acc2, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bhv, acc2, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc2, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc2, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bmv, acc2, 0, 0, 0);
+                // the smaller products go to FP64 every 4 chunks
+                if ((r0 & 63) == 48 || r0 + 16 >= mp) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        sum[v] += (double)acc2[v];
+                        acc2[v] = 0.0f;
+                    }
+                }
             }
 #pragma unroll
             for (int v = 0; v < 16; ++v) sum[v] += (double)acc[v];
         }
-        // records: lane i holds feature i of 16 windows (rows 8 (v/4) + 4 hh + v % 4)
+        // records: lane i holds feature i of 16 windows (rows 8 (v/4) + 4 hh
+        // + v % 4); the 16 norms are summed over the 32 feature lanes together
+        float fv[16], n2[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int w = w0 + 8 * (v / 4) + 4 * hh + (v % 4);
+            const double is = w < nw && kpos[w] >= 0 ? sis[w] : 0.0;
+            fv[v] = (float)(sum[v] * is);
+            n2[v] = fv[v] * fv[v];
+        }
+#pragma unroll
+        for (int off = kMBlk / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) n2[v] += __shfl_xor(n2[v], off, kMBlk);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int w = w0 + 8 * (v / 4) + 4 * hh + (v % 4);
             const int32_t kk = w < nw ? kpos[w] : -1;
-            if (__ballot(kk >= 0) == 0) continue;
-            double is = 0.0;
-            if (kk >= 0) is = q.isig[kk];
-            const float fv = (float)(sum[v] * is);
-            float n2 = fv * fv;
-#pragma unroll
-            for (int off = kMBlk / 2; off > 0; off >>= 1) n2 += __shfl_xor(n2, off, kMBlk);
             if (kk >= 0) {
+                const double is = sis[w];
                 float *rec = (float *)q.F + (int64_t)kk * kRec;
                 // the FP32 sum of 30 squares is within 32 u32 of exact
-                const double nrm = sqrt((double)n2) * (1.0 + 64.0 * 5.9604644775390625e-08) + 1e-30;
+                const double nrm = sqrt((double)n2[v]) * (1.0 + 64.0 * 5.9604644775390625e-08) + 1e-30;
                 // ecomp is per unit of sigma / sigma; the stored value adds
                 // its float rounding and the FP64 sigma's (m + 8) u64
                 const double estore = (5.9604644775390625e-08 + (m + 12.0) * u64) * nrm;
-                const float e = (float)((ecomp * (1.0 + 1e-9) + estore) * (1.0 + 1e-5)) * (1.0f + 2.4e-7f) + 1e-30f;
-                float val = i < kFD ? fv : 0.0f;
+                const float e = (float)(((ecomp + eabs * is) * (1.0 + 1e-9) + estore) * (1.0 + 1e-5)) *
+                                    (1.0f + 2.4e-7f) + 1e-30f;
+                float val = i < kFD ? fv[v] : 0.0f;
                 if (i == kSlotErr) val = e;
                 if (i == kSlotNorm) val = (float)nrm * (1.0f + 2.4e-7f);
                 rec[i] = val;
@@ -860,24 +950,25 @@ int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base) 
     return base[L];
 }
 
-void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bl,
-                  int max_m, hipStream_t s) {
+void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bm,
+                  uint16_t *bl, int max_m, hipStream_t s) {
     const int mp = (max_m + 15) & ~15;
     const unsigned gx = (unsigned)std::min<int64_t>((32 * (int64_t)mp + kBlock - 1) / kBlock, 64);
-    hipLaunchKernelGGL(k_basis, dim3(gx, (unsigned)L), dim3(kBlock), 0, s, len, L, base, bh, bl);
+    hipLaunchKernelGGL(k_basis, dim3(gx, (unsigned)L), dim3(kBlock), 0, s, len, L, base, bh, bm,
+                       bl);
 }
 
 void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                         int64_t ntiles, int max_m, const int64_t *bbase, const uint16_t *bh,
-                        const uint16_t *bl, hipStream_t s) {
+                        const uint16_t *bm, const uint16_t *bl, hipStream_t s) {
     // samples of the tile, padded with zeros for the last block's reads
     const size_t dyn = (size_t)(kTileW + ((max_m + 15) & ~15) + kMBlk) * sizeof(double);
     if (precision == 1)
-        hipLaunchKernelGGL((k_sketch_mfma<3>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, bbase, bh, bl);
+        hipLaunchKernelGGL((k_sketch_mfma<6>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                           tile_off, bbase, bh, bm, bl);
     else
         hipLaunchKernelGGL((k_sketch_mfma<1>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, bbase, bh, bl);
+                           tile_off, bbase, bh, bm, bl);
 }
 
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s) {

@@ -419,11 +419,11 @@ void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_
                    int64_t ntiles, int max_m, hipStream_t s);
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s);
 int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base);
-void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bl,
-                  int max_m, hipStream_t s);
+void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bm,
+                  uint16_t *bl, int max_m, hipStream_t s);
 void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                         int64_t ntiles, int max_m, const int64_t *bbase, const uint16_t *bh,
-                        const uint16_t *bl, hipStream_t s);
+                        const uint16_t *bm, const uint16_t *bl, hipStream_t s);
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);

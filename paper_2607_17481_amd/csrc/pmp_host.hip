@@ -380,8 +380,8 @@ struct Bufs {
     float *emax, *gproj;
     double *cov, *udir;
     GridLen *gl;
-    int64_t *bbase;            // MFMA sketch basis: offsets per length, then hi / lo tables
-    uint16_t *bh, *bl;
+    int64_t *bbase;            // MFMA sketch basis: offsets per length, then hi / mid / lo tables
+    uint16_t *bh, *bm, *bl;
     unsigned int *hist;
     uint32_t *nless;
     RowReq *rows;
@@ -424,6 +424,7 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
         const int64_t ne = basis_elems(p.len.data(), p.L, base);
         b.bbase = take<int64_t>(a, p.L + 1);
         b.bh = take<uint16_t>(a, ne);
+        b.bm = take<uint16_t>(a, ne);
         b.bl = take<uint16_t>(a, ne);
     }
     b.gl = take<GridLen>(a, p.L);
@@ -808,9 +809,9 @@ static int run_pipeline(Run &R, Arena &ar) {
         // precision forms: the projection on the matrix cores
         HIPCHK(hipMemcpyAsync(b.bbase, bbase.data(), (p.L + 1) * sizeof(int64_t),
                               hipMemcpyHostToDevice, s));
-        launch_basis(b.len, p.L, b.bbase, b.bh, b.bl, p.max_m, s);
-        launch_sketch_mfma(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, b.bbase, b.bh, b.bl,
-                           s);
+        launch_basis(b.len, p.L, b.bbase, b.bh, b.bm, b.bl, p.max_m, s);
+        launch_sketch_mfma(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, b.bbase, b.bh, b.bm,
+                           b.bl, s);
     }
     // the join's principal directions (GPU), used by the keys kernel
     if (o.certify && N > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
