@@ -118,7 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restric
 // ------------------------------------------------------------ radix sort
 
 constexpr int kSortRounds = 8;                       // items per thread
-constexpr int kSortTile = kBlock * kSortRounds;      // 2048 per block
+constexpr int kSortTile = kBlock * kSortRounds;      // 2048 per tile
+constexpr int kSortSub = 4;                          // consecutive tiles per block
+constexpr int kSortChunk = kSortTile * kSortSub;     // keys per block
 constexpr int kRadix = 256;
 
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t *__restrict__ keys,
@@ -129,11 +131,34 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t *__restric
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int lane = lane_id();
+    // the block's kSortSub tiles; wavefront w counts the slice [w, w + 1) *
+    // kSortTile / 4 of each.  Equal digits of a round are matched by ballots
+    // (one per digit bit) and counted by one lane, so a tile whose keys share
+    // a digit (as they do after the lower passes) costs one LDS atomic per
+    // round, not 64
+    for (int sub = 0; sub < kSortSub; ++sub) {
+        const int64_t base = (int64_t)blockIdx.x * kSortChunk + (int64_t)sub * kSortTile +
+                             (int64_t)(threadIdx.x / kWave) * (kSortTile / (kBlock / kWave));
+        if (base >= n) break;
+        uint32_t key[kSortRounds];
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+        for (int r = 0; r < kSortRounds; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            key[r] = i < n ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+            const bool valid = base + (int64_t)r * kWave + lane < n;
+            const uint32_t dig = (key[r] >> shift) & mask;
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                const uint64_t bal = __ballot((dig >> b) & 1u);
+                peers &= ((dig >> b) & 1u) ? bal : ~bal;
+            }
+            if (valid && (peers & lanemask_lt()) == 0)
+                atomicAdd(&h[dig], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     // digit-major so that the exclusive scan gives each (digit, block) its
@@ -141,14 +166,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t *__restric
     counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// One tile of kSortTile keys per block; wavefront w takes the contiguous
-// slice [w, w + 1) * kSortTile / 4 in kSortRounds rounds of 64.  Pass 1 ranks
-// each key among the equal digits of its round (one ballot per digit bit) and
-// counts each wavefront's digits; after one block barrier every (wavefront,
-// digit) knows its first output position (the block's offset of the digit
-// plus the counts of the earlier wavefronts); pass 2 writes the keys with no
-// further barrier.  Stable: within a digit, wavefronts, rounds and lanes keep
-// their input order.
+// kSortSub consecutive tiles of kSortTile keys per block, in order; in each
+// tile wavefront w takes the contiguous slice [w, w + 1) * kSortTile / 4 in
+// kSortRounds rounds of 64.  Pass 1 ranks each key among the equal digits of
+// its round (one ballot per digit bit) and counts each wavefront's digits;
+// after one block barrier every (wavefront, digit) knows its first output
+// position (the digit's running position in the block, which starts at the
+// block's offset of the digit, plus the counts of the earlier wavefronts);
+// pass 2 writes the keys.  Stable: within a digit, tiles, wavefronts, rounds
+// and lanes keep their input order.
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift, int nbits,
@@ -158,57 +184,63 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
     const uint32_t mask = (1u << nbits) - 1u;
-    for (int q = 0; q < kW; ++q) wcnt[q][threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / kW);
-    uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
+    // thread d: the next output position of digit d
+    uint32_t run = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    for (int sub = 0; sub < kSortSub; ++sub) {
+        const int64_t tbase = (int64_t)blockIdx.x * kSortChunk + (int64_t)sub * kSortTile;
+        if (tbase >= n) break;
+        for (int q = 0; q < kW; ++q) wcnt[q][threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t base = tbase + (int64_t)w * (kSortTile / kW);
+        uint32_t key[kSortRounds], val[kSortRounds], rank[kSortRounds];
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        key[r] = valid ? kin[i] : 0u;
-        val[r] = valid ? vin[i] : 0u;
-    }
+        for (int r = 0; r < kSortRounds; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            const bool valid = i < n;
+            key[r] = valid ? kin[i] : 0u;
+            val[r] = valid ? vin[i] : 0u;
+        }
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        const uint32_t dig = (key[r] >> shift) & mask;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < nbits; ++b) {
-            const uint64_t bal = __ballot((dig >> b) & 1u);
-            peers &= ((dig >> b) & 1u) ? bal : ~bal;
+        for (int r = 0; r < kSortRounds; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            const bool valid = i < n;
+            const uint32_t dig = (key[r] >> shift) & mask;
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                const uint64_t bal = __ballot((dig >> b) & 1u);
+                peers &= ((dig >> b) & 1u) ? bal : ~bal;
+            }
+            const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
+            // the digit's count so far in this wavefront (earlier rounds) plus the
+            // equal digits of earlier lanes; the leader then adds the round's count
+            rank[r] = below + (valid ? wcnt[w][dig] : 0u);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (valid && below == 0) wcnt[w][dig] += (uint32_t)__popcll(peers);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
-        // the digit's count so far in this wavefront (earlier rounds) plus the
-        // equal digits of earlier lanes; the leader then adds the round's count
-        rank[r] = below + (valid ? wcnt[w][dig] : 0u);
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (valid && below == 0) wcnt[w][dig] += (uint32_t)__popcll(peers);
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    {
-        // thread d: the first position of digit d for each wavefront
-        const int d = threadIdx.x;
-        uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
-        for (int q = 0; q < kW; ++q) {
-            const uint32_t c = wcnt[q][d];
-            wcnt[q][d] = run;
-            run += c;
+        __syncthreads();
+        {
+            // thread d: the first position of digit d for each wavefront
+            const int d = threadIdx.x;
+            for (int q = 0; q < kW; ++q) {
+                const uint32_t c = wcnt[q][d];
+                wcnt[q][d] = run;
+                run += c;
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kWave + lane;
-        if (i < n) {
-            const uint32_t pos = wcnt[w][(key[r] >> shift) & mask] + rank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+        for (int r = 0; r < kSortRounds; ++r) {
+            const int64_t i = base + (int64_t)r * kWave + lane;
+            if (i < n) {
+                const uint32_t pos = wcnt[w][(key[r] >> shift) & mask] + rank[r];
+                kout[pos] = key[r];
+                vout[pos] = val[r];
+            }
         }
+        __syncthreads();                                 // wcnt is cleared next
     }
 }
 
@@ -235,7 +267,7 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
 }
 
 size_t sort_temp_bytes(int64_t n) {
-    int64_t nb = cdiv(n, kSortTile);
+    int64_t nb = cdiv(n, kSortChunk);
     size_t counts = (size_t)(nb * kRadix) * sizeof(uint32_t);
     return 2 * counts + scan_temp_bytes(nb * kRadix) + 256;
 }
@@ -243,7 +275,7 @@ size_t sort_temp_bytes(int64_t n) {
 void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
                       int lo, int hi, void *temp, hipStream_t s) {
     if (n <= 1 || hi <= lo) return;
-    int64_t nb = cdiv(n, kSortTile);
+    int64_t nb = cdiv(n, kSortChunk);
     uint32_t *counts = (uint32_t *)temp;
     uint32_t *offs = counts + nb * kRadix;
     void *stemp = (void *)(offs + nb * kRadix);
