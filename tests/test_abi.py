@@ -45,6 +45,8 @@ def test_workspace_query_and_argument_checks():
     assert pmp.workspace_bytes(100, 2, 10) == 0          # m_min < 3
     assert pmp.workspace_bytes(100, 10, 101) == 0        # m_max > n
     assert pmp.workspace_bytes(100, 20, 10) == 0
+    assert pmp.workspace_bytes(10_000, 100, 2048) > 0     # the longest supported window
+    assert pmp.workspace_bytes(10_000, 100, 2049) == 0
     with pytest.raises(pmp.PMPError) as e:
         pmp.open_host(np.zeros(10), 2, 5, 3, 1)
     assert e.value.code == pmp.PMP_EINVAL

@@ -403,6 +403,23 @@ def test_ragged_and_extreme_lengths(gpu, ws, oracle, n, lo, hi, excl):
     assert ok, msg
 
 
+_MAXLEN_ROWS: dict = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_longest_supported_windows(gpu, ws, oracle, prec):
+    """Windows of the longest supported length (2048, where the sketch and
+    probe kernels hold their largest LDS tiles), against the full oracle
+    profile."""
+    n, lo, hi, excl = 4500, 2046, 2048, 1024
+    t = np.cumsum(np.random.default_rng(n).standard_normal(n))
+    if not _MAXLEN_ROWS:
+        _MAXLEN_ROWS.update(oracle.pan_profile(t, range(lo, hi + 1), excl))
+    res, _ = run(gpu, ws, t, lo, hi, excl, precision=PRECS[prec])
+    ok, msg = parity.check_topk(res, _MAXLEN_ROWS, 20, oracle, t)
+    assert ok, msg
+
+
 def test_invalid_arguments(gpu):
     t = np.random.default_rng(0).standard_normal(100)
     with pytest.raises(gpu.PMPError) as e:
