@@ -122,13 +122,15 @@ __global__ __launch_bounds__(kBlock) void k_select_emit(const uint64_t *__restri
 
 // ------------------------------------------------------------------ rows
 
-// Pass 1 (find_min = 1): out_min[c] = min over valid j of the snapped
-// distance.  Pass 2: out_arg[c] = smallest valid j whose snapped distance
-// equals req[c].target.  Constant windows are not indexed and never scanned.
+// One pass over each requested row c: out_min[c] = min over valid j of the
+// snapped distance (the certificate's check), and out_arg[c] = smallest
+// valid j whose snapped distance equals req[c].target (the reported
+// neighbour when the check holds).  Constant windows are not indexed and
+// never scanned.
 // Each lane takes every (threads)-th window of the length and evaluates the
 // canonical distance on its own (lane_zdist): neighbouring lanes read
 // neighbouring windows, and the row's own window is shared by all.
-__global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict__ rr, int find_min,
+__global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict__ rr,
                                                  unsigned long long *__restrict__ out_min,
                                                  unsigned long long *__restrict__ out_arg) {
     const RowReq R = rr[blockIdx.y];
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict
     const int64_t i = (int64_t)q.cell[R.k] - L.cell_base;
     const double mui = q.mu[R.k], isi = q.isig[R.k];
     const int64_t nt = (int64_t)gridDim.x * kBlock;
-    unsigned long long best = find_min ? (unsigned long long)kInfBits : ~0ull;
+    unsigned long long best = (unsigned long long)kInfBits, arg = ~0ull;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < L.n_index; x += nt) {
         const int64_t kc = L.kbase + x;
         const int64_t j = (int64_t)q.cell[kc] - L.cell_base;
@@ -145,16 +147,18 @@ __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict
         if (gap < q.excl) continue;
         const double dd = snap(lane_zdist(q.t, i, mui, isi, j, q.mu[kc], q.isig[kc], m));
         const unsigned long long b = (unsigned long long)dbits(dd);
-        if (find_min) best = b < best ? b : best;
-        else if (b == R.target && (unsigned long long)j < best) best = (unsigned long long)j;
+        best = b < best ? b : best;
+        if (b == R.target && (unsigned long long)j < arg) arg = (unsigned long long)j;
     }
     for (int off = 1; off < kWave; off <<= 1) {
         const unsigned long long o = __shfl_xor(best, off, kWave);
+        const unsigned long long a = __shfl_xor(arg, off, kWave);
         best = o < best ? o : best;
+        arg = a < arg ? a : arg;
     }
     if (lane_id() == 0) {
-        if (find_min) atomicMin(&out_min[blockIdx.y], best);
-        else if (best != ~0ull) atomicMin(&out_arg[blockIdx.y], best);
+        atomicMin(&out_min[blockIdx.y], best);
+        if (arg != ~0ull) atomicMin(&out_arg[blockIdx.y], arg);
     }
 }
 
@@ -205,11 +209,11 @@ void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t n
                        pivot, need, off, less, less_val, nless, cap, eq);
 }
 
-void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
+void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s) {
     if (nrows <= 0) return;
     hipLaunchKernelGGL(k_rows, dim3(gridcap(maxN, 1024), (unsigned)nrows), dim3(kBlock), 0, s,
-                       q, rr, find_min, out_min, out_arg);
+                       q, rr, out_min, out_arg);
 }
 
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,

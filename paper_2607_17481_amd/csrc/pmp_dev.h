@@ -453,7 +453,7 @@ void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uin
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
                        const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
                        int cb3, double T, hipStream_t s);
-void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN, int find_min,
+void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,

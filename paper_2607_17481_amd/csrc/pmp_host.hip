@@ -949,10 +949,13 @@ static int run_pipeline(Run &R, Arena &ar) {
         HIPCHK(hipMemcpyAsync(b.rows, rr.data(), nacc * sizeof(RowReq), hipMemcpyHostToDevice, s));
         launch_fill_u64((uint64_t *)b.row_min, nacc, kInfBits, s);
         launch_fill_u64((uint64_t *)b.row_arg, nacc, ~0ull, s);
+        // each reported cell's exact row: its minimum (checked against the
+        // certified value) and the smallest neighbour attaining that value
+        launch_rows(q, b.rows, nacc, maxN, b.row_min, b.row_arg, s);
+        HIPCHK(hipMemcpyAsync(rmin.data(), b.row_min, nacc * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(rarg.data(), b.row_arg, nacc * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
         if (o.certify) {
-            launch_rows(q, b.rows, nacc, maxN, 1, b.row_min, b.row_arg, s);
-            HIPCHK(hipMemcpyAsync(rmin.data(), b.row_min, nacc * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
             for (int x = 0; x < nacc; ++x)
                 if (rmin[x] != rr[x].target) {
                     double a, bq;
@@ -964,8 +967,6 @@ static int run_pipeline(Run &R, Arena &ar) {
                                 p.ms[acc[x].l], (long long)acc[x].i, a, bq);
                 }
         }
-        launch_rows(q, b.rows, nacc, maxN, 0, b.row_min, b.row_arg, s);
-        HIPCHK(hipMemcpyAsync(rarg.data(), b.row_arg, nacc * 8, hipMemcpyDeviceToHost, s));
     }
     tm.mark(7, s);
     HIPCHK(hipStreamSynchronize(s));
