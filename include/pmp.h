@@ -52,12 +52,18 @@ typedef struct {
     double  dist;
 } pmp_motif;
 
-/* Precision of the cached spectral features (Sec. 3.2 "Features are cached in
- * single precision").  Exact distances are always computed in FP64. */
+/* Precision of the spectral sketch and the cached features (Sec. 3.2, where
+ * features are cached in single precision).  Moments, exact distances and
+ * the certificate's verification are FP64 in every form, and every stored
+ * feature vector carries a derived bound e_i on its error, which the
+ * Parseval prune subtracts, so it stays a true lower bound. */
 enum {
-    PMP_PREC_FP64 = 0,  /* plain form: FP64 features, FP64 bound            */
-    PMP_PREC_FP32 = 1,  /* FP32 features, bound shrunk by a derived margin  */
-    PMP_PREC_BF16 = 2   /* FP32 features for the bound, BF16 MFMA keys      */
+    PMP_PREC_FP64 = 0,  /* plain form: FP64 sliding DFT, FP64 features       */
+    PMP_PREC_FP32 = 1,  /* windows x DFT basis on the matrix cores, both
+                           split exactly into three bf16 parts (six products,
+                           FP32 accumulation): FP32-grade features           */
+    PMP_PREC_BF16 = 2   /* the same product in plain bf16 (one product,
+                           FP32 accumulation): a wider margin                */
 };
 
 typedef struct {
@@ -110,8 +116,9 @@ typedef struct {
  * valid pairs |i-j| >= exclusion, occupancy target budget (alpha, the paper's
  * only user knob).  out: caller-owned, capacity k; *n_out = number written
  * (< k when fewer finite cells exist).  The series is copied before return.
- * Errors: PMP_EINVAL unless 3 <= m_min <= m_max <= n, k >= 1, exclusion >= 1,
- * budget >= 1 and every sample is finite. */
+ * Errors: PMP_EINVAL unless 3 <= m_min <= m_max <= n, m_max <= 2048 (the
+ * longest window supported), k >= 1, exclusion >= 1, budget >= 1 and every
+ * sample is finite. */
 int pmp_open(const double *series, int64_t n, int32_t m_min, int32_t m_max,
              int32_t k, int32_t exclusion, int32_t budget,
              pmp_motif *out, int32_t *n_out);
