@@ -112,12 +112,23 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
     int pr = -1, budget = q.budget_R;
     int64_t bs = 0, cut = 0, span = 0;
     int take = 0, rec = 0, str = 1, j = 0;
-    // current proposals (two slots)
+    // current proposals (two slots), kept in LDS from the search that finds
+    // them to the verification that reads them, so that they hold no
+    // registers through the search loop
+    __shared__ double s_Pc[2][kWave], s_mu[2][kWave], s_is[2][kWave], s_lim[2][kWave];
+    __shared__ int64_t s_ic[2][kWave];
+    __shared__ uint32_t s_c[2][kWave];
+    const int ln = threadIdx.x;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        s_Pc[sl][ln] = 0.0;
+        s_mu[sl][ln] = 0.0;
+        s_is[sl][ln] = 0.0;
+        s_lim[sl][ln] = INFINITY;
+        s_ic[sl][ln] = 0;
+        s_c[sl][ln] = 0;
+    }
     bool has = false, has1 = false;
-    uint32_t pc = 0, pc1 = 0;
-    int64_t pic = 0, pic1 = 0;
-    double pPc = 0.0, pmu = 0.0, pis = 0.0, plim = INFINITY;
-    double pPc1 = 0.0, pmu1 = 0.0, pis1 = 0.0, plim1 = INFINITY;
 
     for (;;) {
         // ---- the wavefront searches until every lane still working holds a
@@ -169,27 +180,23 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
                 const float lb = lb_mem<FT>(fq, (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
                 if ((double)lb >= thr) continue;
             }
-            if (!has) {
-                has = true;
-                plim = exit_bound(thr);
-                pc = kc;
-                pic = (int64_t)q.pcell[cs] - cell_base;
-                pPc = Pc;
-                pmu = q.mu[kc];
-                pis = q.isig[kc];
-            } else {
-                has1 = true;
-                plim1 = exit_bound(thr);
-                pc1 = kc;
-                pic1 = (int64_t)q.pcell[cs] - cell_base;
-                pPc1 = Pc;
-                pmu1 = q.mu[kc];
-                pis1 = q.isig[kc];
+            {
+                const int sl = has ? 1 : 0;
+                s_lim[sl][ln] = exit_bound(thr);
+                s_c[sl][ln] = kc;
+                s_ic[sl][ln] = (int64_t)q.pcell[cs] - cell_base;
+                s_Pc[sl][ln] = Pc;
+                s_mu[sl][ln] = q.mu[kc];
+                s_is[sl][ln] = q.isig[kc];
+                if (has) has1 = true; else has = true;
             }
         }
         // ---- the wavefront verifies the first proposals
         const uint64_t mask = __ballot(has);
         if (mask == 0) break;
+        const double pPc = s_Pc[0][ln], pmu = s_mu[0][ln], pis = s_is[0][ln], plim = s_lim[0][ln];
+        const int64_t pic = s_ic[0][ln];
+        const uint32_t pc = s_c[0][ln];
         auto on_result = [&](double dd) {
             ++n_ver;
             const unsigned long long db = (unsigned long long)dbits(dd);
@@ -209,6 +216,8 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
         // the second slot (a lane whose own cell reached 0 drops it)
         const uint64_t mask1 = __ballot(has1 && !done);
         auto on_result1 = [&](double dd) {
+            const double pPc1 = s_Pc[1][ln];
+            const uint32_t pc1 = s_c[1][ln];
             ++n_ver;
             const unsigned long long db = (unsigned long long)dbits(dd);
             if (dd < Pq) {
@@ -219,6 +228,8 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
             if (Pq == 0.0) done = true;
         };
         if (mask1) {
+            const double pmu1 = s_mu[1][ln], pis1 = s_is[1][ln], plim1 = s_lim[1][ln];
+            const int64_t pic1 = s_ic[1][ln];
             if (staged)
                 verify_proposals(mask1, QwinA{qlo}, q.t, iq, muq, isq, pic1, pmu1, pis1, m, on_result1,
                                  plim1);
