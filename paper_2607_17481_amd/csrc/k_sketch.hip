@@ -936,12 +936,11 @@ void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_
     // sized for the longest window of the request
     const int st_len = (kTileW + max_m + 1) & ~1;
     const size_t dyn = (size_t)(st_len + kRowsC * kStageLd) * sizeof(double);
-    if (precision == 0)
-        hipLaunchKernelGGL((k_sketch<double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, st_len);
-    else
-        hipLaunchKernelGGL((k_sketch<float>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, st_len);
+    // the FP64 form only: the precision forms sketch on the matrix cores
+    // (k_sketch_mfma)
+    (void)precision;
+    hipLaunchKernelGGL((k_sketch<double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                       tile_off, st_len);
 }
 
 int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base) {
