@@ -309,13 +309,15 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
 
     tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, sm.kpos, sm.widx, sm.wsum);
     // ---- per chunk, the staging rows that hold a non-constant window;
-    // wavefront wv lists chunks 2 wv and 2 wv + 1 (row = segment * 8 + slide)
+    // wavefront wv lists its share of the chunks (row = segment * kSlidesC +
+    // slide), kWave rows at a time
+    constexpr int kChunksW = kSegW / kSlidesC / (kBlock / kWave);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int chunk = 2 * wv + h;
+    for (int h = 0; h < kChunksW; ++h) {
+        const int chunk = kChunksW * wv + h;
         int base = 0;
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
+        for (int half = 0; half < kRowsC / kWave; ++half) {
             const int row = half * kWave + lane;
             const int s = (row / kSlidesC) * kSegW + chunk * kSlidesC + (row % kSlidesC);
             const bool ix = s < nw && sm.kpos[s] >= 0;
