@@ -678,7 +678,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // length (blk_base), so the length's projections sit in LDS for all threads.
 namespace {
 struct KeysSmem {
-    uint16_t gh[32][32], gl[32][32];          // SimHash projections (bit x feature), bf16 hi, lo
+    // SimHash projections (bit x feature), bf16 hi, lo; rows of 40 (80 bytes,
+    // an odd multiple of 16) so that the lanes' 16-byte reads of different
+    // rows fall in different banks
+    uint16_t gh[32][40], gl[32][40];
     float dots[kBlock / kWave][2][32][33];    // each wavefront's 64 x 32 projections
     double u[kJoinDirs][32];                  // the join's principal directions
 };
