@@ -1,6 +1,6 @@
 """Comparison helpers for the GPU parity tests (test infrastructure).
 
-Bar (the benchmark spec): top-k index sets bit-exact, ties within 1e-9 relative
+Bar: top-k index sets bit-exact, ties within 1e-9 relative
 allowed; distances within 1e-6 relative (values below the 1e-6 zero snap are
 both 0).
 """
