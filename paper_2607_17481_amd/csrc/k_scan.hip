@@ -272,9 +272,9 @@ size_t sort_temp_bytes(int64_t n) {
     return 2 * counts + scan_temp_bytes(nb * kRadix) + 256;
 }
 
-void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
-                      int lo, int hi, void *temp, hipStream_t s) {
-    if (n <= 1 || hi <= lo) return;
+int radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
+                     int lo, int hi, void *temp, hipStream_t s, bool copy_back) {
+    if (n <= 1 || hi <= lo) return 0;
     int64_t nb = cdiv(n, kSortChunk);
     uint32_t *counts = (uint32_t *)temp;
     uint32_t *offs = counts + nb * kRadix;
@@ -292,10 +292,12 @@ void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, in
         t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
-    if (passes & 1) {
+    if ((passes & 1) && copy_back) {
         (void)hipMemcpyAsync(k0, ka, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
         (void)hipMemcpyAsync(v0, va, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        return 0;
     }
+    return passes & 1;
 }
 
 }  // namespace pmp

@@ -897,7 +897,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
 // First slot of every bucket from the sorted keys: between two consecutive
 // sorted entries, every bucket index in (previous, current] starts at the
 // current slot (empty buckets included); the entry past the end closes the
-// last buckets.
+// last buckets.  Also the slot map: slot -> cell.
 __global__ __launch_bounds__(kBlock) void k_bucket_bounds(Req q, int64_t N, int64_t nbuckets,
                                                           uint32_t *__restrict__ bstart) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -911,13 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_bounds(Req q, int64_t N, int6
     const int64_t cur = s < N ? gidx(q.skey[s]) : nbuckets;
     const int64_t prev = s > 0 ? gidx(q.skey[s - 1]) : -1;
     for (int64_t b = prev + 1; b <= cur; ++b) bstart[b] = (uint32_t)s;
-}
-
-// Slot map after the sort: slot -> cell.
-__global__ __launch_bounds__(kBlock) void k_slot_maps(Req q, int64_t N) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= N) return;
-    q.pcell[s] = q.cell[q.perm[s]];
+    if (s < N) q.pcell[s] = q.cell[q.perm[s]];
 }
 
 // ------------------------------------------------------------ launchers
@@ -988,10 +982,5 @@ void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *b
     hipLaunchKernelGGL(k_bucket_bounds, dim3(nblk(N + 1)), dim3(kBlock), 0, s, q, N, nbuckets,
                        bstart);
 }
-
-void launch_slot_maps(const Req &q, int64_t N, hipStream_t s) {
-    if (N > 0) hipLaunchKernelGGL(k_slot_maps, dim3(nblk(N)), dim3(kBlock), 0, s, q, N);
-}
-
 
 }  // namespace pmp

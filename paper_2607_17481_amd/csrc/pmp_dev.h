@@ -407,9 +407,11 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
                         void *temp, hipStream_t s);
 size_t sort_temp_bytes(int64_t n);
 // Stable LSD radix sort of (key, val) pairs on key bits [lo, hi).  Result in
-// (k0, v0); (k1, v1) are scratch of the same size.
-void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                      int64_t n, int lo, int hi, void *temp, hipStream_t s);
+// (k0, v0), or, after an odd number of passes with copy_back false, in
+// (k1, v1): the return value is 1 then, 0 otherwise.  (k1, v1) are scratch
+// of the same size.
+int radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n,
+                     int lo, int hi, void *temp, hipStream_t s, bool copy_back = true);
 
 // (k_sketch.hip)
 void launch_changepoints(const double *t, int64_t n, uint32_t *flag, int *bad, hipStream_t s);
@@ -426,7 +428,6 @@ void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const ui
                         const uint16_t *bm, const uint16_t *bl, hipStream_t s);
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
-void launch_slot_maps(const Req &q, int64_t N, hipStream_t s);
 // (k_probe.hip)
 void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, int max_m,
                   hipStream_t s);

@@ -817,9 +817,14 @@ static int run_pipeline(Run &R, Arena &ar) {
     if (o.certify && N > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
     launch_keys(o.precision, q, p.nkblocks, s);
     tm.mark(2, s);
-    radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits, b.sort_tmp, s);
+    if (radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits,
+                         b.sort_tmp, s, false)) {
+        // an odd number of passes leaves the sorted pairs in the scratch pair
+        q.skey = b.skey2;
+        q.sval = b.sval2;
+        q.perm = b.sval2;
+    }
     launch_bucket_bounds(q, N, p.nbuckets, b.bstart, s);
-    launch_slot_maps(q, N, s);
     launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
     tm.mark(3, s);
     tm.mark(4, s);
@@ -1010,7 +1015,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                                       0, d->keys);
         }
         if (d->perm && N)
-            hipLaunchKernelGGL(k_debug_perm, dim3(gb), dim3(256), 0, s, b.sval, b.cell, N, d->perm);
+            hipLaunchKernelGGL(k_debug_perm, dim3(gb), dim3(256), 0, s, q.perm, b.cell, N, d->perm);
         if (d->bucket_start)
             HIPCHK(hipMemcpyAsync(d->bucket_start, b.bstart, (p.nbuckets + 1) * 4,
                                   hipMemcpyDeviceToDevice, s));
