@@ -238,6 +238,62 @@ def serving_sweep(cfg):
     print(json.dumps(out), flush=True)
 
 
+PARAM_SWEEP = {"alpha": (4, 8, 16, 32, 64), "K": (4, 8, 12, 16), "maxperf": (4, 4)}
+
+
+def param_sweep(workload, precision, steps=2):
+    """Runtime against the occupancy target alpha (spectral width calibrated)
+    and against the spectral width K (alpha = 16), and at alpha = 4, K = 4
+    (the paper's maximum-performance constants that apply here; its anchor
+    stride and P_max have no counterpart).  The exact top-k is the same in
+    every configuration (Prop. 2); each run is checked against the default
+    one."""
+    import torch
+    from paper_2607_17481_amd import pmp
+    gen, n, seed, m_min, m_max, step, excl, k = WORKLOADS[workload]
+    t = make_series(workload)
+    cells = synth.cells(n, range(m_min, m_max + 1, step))
+    dev = torch.device("cuda:0")
+    td = torch.from_numpy(t).to(dev)
+    ws = pmp.Workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def run(alpha, K):
+        o = pmp.options(m_step=step, precision=PREC[precision], spectral_width=K)
+        pmp.run_device(td, m_min, m_max, k, excl, alpha, o, ws, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res, st = pmp.run_device(td, m_min, m_max, k, excl, alpha, o, ws, stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = {"alpha": alpha, "K": st["K"], "ms_per_step": ms, "value": cells * 1e3 / ms,
+             "phase_ms": {p: st["ms_" + p] for p in ("sketch", "sort", "probe", "join", "rows")},
+             "pass_candidates": st["pass_candidates"], "pass_verified": st["pass_verified"],
+             "join_candidates": st["join_candidates"], "join_verified": st["join_verified"],
+             "certify_rounds": st["certify_rounds"]}
+        print(f"  alpha {alpha} K {st['K']}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        return r, [(x.i, x.j, x.m, x.dist) for x in res]
+
+    base, ref = run(16, 0)
+    out = {"metric": "runtime against alpha and K", "workload": workload, "precision": precision,
+           "cells": cells, "steps": steps, "default": base, "alpha": [], "K": [], "maxperf": None}
+    same = True
+    for a in PARAM_SWEEP["alpha"]:
+        r, top = run(a, 0)
+        same &= top == ref
+        out["alpha"].append(r)
+    for K in PARAM_SWEEP["K"]:
+        r, top = run(16, K)
+        same &= top == ref
+        out["K"].append(r)
+    r, top = run(*PARAM_SWEEP["maxperf"])
+    same &= top == ref
+    out["maxperf"] = r
+    out["same_top_k"] = same
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +308,8 @@ def main():
                     help="only run the copy kernel that scales the HBM counters")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the serving measurement at 0.5 / 0.8 / 1.0 of capacity")
+    ap.add_argument("--param-sweep", action="store_true",
+                    help="only run the alpha / K sweep on --workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the workload fits one MI355X); "
@@ -262,6 +320,9 @@ def main():
         return
     if args.serving_sweep:
         serving_sweep(SERVING_SWEEP)
+        return
+    if args.param_sweep:
+        param_sweep(args.workload, args.precision)
         return
 
     import torch
