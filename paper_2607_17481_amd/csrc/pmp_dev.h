@@ -110,17 +110,6 @@ __device__ __forceinline__ int find_len(const LenInfo *len, int L, int64_t cell)
     return lo;
 }
 
-// Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on
-// XCD b mod 8), each XCD with its own L2.  This maps the launch order onto
-// work order so that every XCD takes one contiguous range of the work, and
-// neighbouring work items, which read neighbouring data, share an L2.
-__device__ __forceinline__ uint32_t xcd_block() {
-    constexpr uint32_t kXcds = 8;
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
-    return x * q + min(x, r) + b / kXcds;
-}
-
 // Length index of an indexed position k (slots share the per-length ranges).
 __device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) {
     int lo = 0, hi = L - 1;
