@@ -217,14 +217,18 @@ SERVING_SWEEP = {"requests": 120, "n_lo": 10_000, "n_hi": 2_000_000, "slots": 4,
                  "hbm_budget_gb": 192, "loads": (0.5, 0.8, 1.0)}
 
 
-def serving_sweep(cfg):
+def serving_sweep(cfg, capacity=None):
     """The serving measurement over offered loads: requests with series
     lengths log-uniform up to 2e6, FP64 form, open loop at each fraction of
-    the closed-loop capacity.  Progress goes to stderr, one line per run."""
+    the closed-loop capacity (measured first, all requests at once, unless
+    given).  Progress goes to stderr, one line per run."""
     reqs = synth.serving_requests(cfg["requests"], 1.0, cfg["n_lo"], cfg["n_hi"])
     series = [r.series() for r in reqs]
     budget = cfg["hbm_budget_gb"] << 30
-    cap = serving_run(0, reqs, series, 0.0, cfg["slots"], budget, True)["req_per_s"]
+    if capacity is None:
+        cap = serving_run(0, reqs, series, 0.0, cfg["slots"], budget, True)["req_per_s"]
+    else:
+        cap = capacity
     print(f"capacity {cap:.3f} req/s", file=sys.stderr, flush=True)
     out = {"metric": "serving latency over offered load", "form": "fp64",
            "requests": len(reqs), "n_range": [cfg["n_lo"], cfg["n_hi"]], "slots": cfg["slots"],
@@ -308,6 +312,12 @@ def main():
                     help="only run the copy kernel that scales the HBM counters")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the serving measurement at 0.5 / 0.8 / 1.0 of capacity")
+    ap.add_argument("--sweep-requests", type=int, default=SERVING_SWEEP["requests"],
+                    help="requests of the serving sweep")
+    ap.add_argument("--sweep-loads", default=",".join(str(x) for x in SERVING_SWEEP["loads"]),
+                    help="offered loads of the serving sweep, as fractions of capacity")
+    ap.add_argument("--sweep-capacity", type=float, default=None,
+                    help="capacity (requests/s) to take instead of measuring it")
     ap.add_argument("--param-sweep", action="store_true",
                     help="only run the alpha / K sweep on --workload")
     args = ap.parse_args()
@@ -319,7 +329,9 @@ def main():
         copy_calibration()
         return
     if args.serving_sweep:
-        serving_sweep(SERVING_SWEEP)
+        cfg = dict(SERVING_SWEEP, requests=args.sweep_requests,
+                   loads=tuple(float(x) for x in args.sweep_loads.split(",")))
+        serving_sweep(cfg, args.sweep_capacity)
         return
     if args.param_sweep:
         param_sweep(args.workload, args.precision)
