@@ -95,7 +95,7 @@ def _ecg_rows(oracle, t, m, excl, starts):
     return [_ECG_ROWS[(m, int(i))] for i in starts]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_ecg1m_full_size(gpu, ws, oracle, prec):
     """The precision-form workload at full size (ECG-like, 1M samples, m =
     100..400 step 6, exclusion 100, top-20), as the benchmark runs it.  The
@@ -117,6 +117,8 @@ def test_ecg1m_full_size(gpu, ws, oracle, prec):
         assert r.m in lengths and abs(r.i - r.j) >= excl
         assert not any(a.m == r.m and 2 * abs(a.i - r.i) <= r.m for a in res[:x])
         p, j = _ecg_rows(oracle, t, r.m, excl, [r.i])[0]
+        print(f"ecg1m {prec} motif {x}: i={r.i} j={r.j} m={r.m} dist={r.dist!r} "
+              f"oracle={p!r} rel_err={abs(r.dist - p) / p if p else abs(r.dist):.3g}")
         assert parity.dist_close(r.dist, p), (r, p)
         if r.j != j:
             assert parity.dist_close(oracle.snap(oracle.distance(t, r.m, r.i, r.j)), p), (r, j)
