@@ -117,8 +117,9 @@ typedef struct {
  * only user knob).  out: caller-owned, capacity k; *n_out = number written
  * (< k when fewer finite cells exist).  The series is copied before return.
  * Errors: PMP_EINVAL unless 3 <= m_min <= m_max <= n, m_max <= 2048 (the
- * longest window supported), k >= 1, exclusion >= 1, budget >= 1 and every
- * sample is finite. */
+ * longest window supported), k >= 1, exclusion >= 1, budget >= 1, every
+ * sample is finite and there are at most 2^31 - 1 cells (about 500 bytes of
+ * workspace each bound the size one GPU holds well below that). */
 int pmp_open(const double *series, int64_t n, int32_t m_min, int32_t m_max,
              int32_t k, int32_t exclusion, int32_t budget,
              pmp_motif *out, int32_t *n_out);

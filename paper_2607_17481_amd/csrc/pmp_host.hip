@@ -687,7 +687,8 @@ static int run_pipeline(Run &R, Arena &ar) {
     const Opt &o = R.o;
     Plan p;
     plan_lengths(p, R.n, R.m_min, R.m_max, o.m_step);
-    if (p.cells >= (int64_t)UINT32_MAX - 1) return fail(PMP_EINVAL, "too many cells (%lld)", (long long)p.cells);
+    // cells are numbered in uint32 and indexed windows in int32
+    if (p.cells > (int64_t)INT32_MAX) return fail(PMP_EINVAL, "too many cells (%lld > 2^31 - 1)", (long long)p.cells);
     Bufs b;
     carve1(ar, b, p, R.k);
     if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
