@@ -405,6 +405,27 @@ def test_ragged_and_extreme_lengths(gpu, ws, oracle, n, lo, hi, excl):
     assert ok, msg
 
 
+_KSWEEP_ROWS: dict = {}
+
+
+@pytest.mark.parametrize("k", [1, 3, 150])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_k_from_one_to_many(gpu, ws, oracle, prec, k):
+    """k = 1, a few, and 150 motifs, whose greedy selection (Sec. 3.6) reaches
+    far down the profile (the 150th distance is 1.04 against 0.72 for the
+    first), so the certificate's threshold join covers far more pairs;
+    against the full oracle profile."""
+    n, lo, hi, excl = 3000, 20, 40, 10
+    t = np.cumsum(np.random.default_rng(77).standard_normal(n))
+    if not _KSWEEP_ROWS:
+        _KSWEEP_ROWS.update(oracle.pan_profile(t, range(lo, hi + 1), excl))
+    res, st = run(gpu, ws, t, lo, hi, excl, k=k, precision=PRECS[prec])
+    assert len(res) == k
+    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, k, oracle, t)
+    assert ok, msg
+    print(f"k={k} {prec}: certify rounds {st['certify_rounds']}")
+
+
 _MAXLEN_ROWS: dict = {}
 
 
