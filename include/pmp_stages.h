@@ -42,6 +42,12 @@ typedef struct {
                                all ones for constant windows                   */
     uint32_t *perm;         /* [sum indexed] bucket order: slot -> cell         */
     uint32_t *bucket_start; /* [sum 2^depth + 1] first slot of every bucket     */
+    /* in: 0 = off.  A value in (0, 1) starts the certificate's threshold
+       loop at that fraction of the one-pass threshold T.  The result stays
+       exact (the loop raises T to the k-th selected value until the greedy
+       prefix lies within it, Sec. 3.6), so this forces the rounds after the
+       first, which real data reaches only rarely.  Other values: EINVAL. */
+    double   t_start_scale;
 } pmp_debug;
 
 int pmp_run_device_debug(const double *d_series, int64_t n, int32_t m_min,

@@ -849,6 +849,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     if (rc) return rc;
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
+    if (R.dbg && R.dbg->t_start_scale > 0.0 && std::isfinite(T)) T *= R.dbg->t_start_scale;
     if (o.certify && N > 0) {
         std::vector<float> emax(p.L);
         HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1072,6 +1073,8 @@ static int run_device(const double *d_series, int64_t n, int32_t m_min, int32_t 
     if (!d_series || !out || !n_out) return fail(PMP_EINVAL, "null argument");
     if (stats && stats->size != sizeof(pmp_stats)) return fail(PMP_EINVAL, "pmp_stats.size mismatch");
     if (dbg && dbg->size != sizeof(pmp_debug)) return fail(PMP_EINVAL, "pmp_debug.size mismatch");
+    if (dbg && !(dbg->t_start_scale >= 0.0 && dbg->t_start_scale < 1.0))
+        return fail(PMP_EINVAL, "pmp_debug.t_start_scale must lie in [0, 1)");
     int rc = check_args(n, m_min, m_max, k, excl, budget);
     if (rc) return rc;
     Run R{};

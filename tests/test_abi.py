@@ -69,3 +69,31 @@ def test_width_calibration_rules():
     k_noise = pmp.calibrate_width(noise, 50, 100)
     assert 4 <= k_smooth < k_noise <= 16
     assert k_noise == 16
+
+
+def test_struct_layouts_match_the_headers(tmp_path):
+    """The binding's ctypes structures have the size and field offsets that a
+    C compiler gives the header's structs."""
+    import subprocess
+    from paper_2607_17481_amd import pmp
+    pairs = [("pmp_motif", pmp.MotifC), ("pmp_options", pmp.Options), ("pmp_stats", pmp.Stats),
+             ("pmp_timing", pmp.Timing), ("pmp_debug", pmp.Debug)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pmp_stages.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} (sizeof) %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict()
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, v = ln.split()
+        got[(cname, field)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "(sizeof)")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -426,6 +426,32 @@ def test_k_from_one_to_many(gpu, ws, oracle, prec, k):
     print(f"k={k} {prec}: certify rounds {st['certify_rounds']}")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_threshold_loop_past_first_round(gpu, ws, oracle, prec):
+    """The certificate's threshold loop (Sec. 3.6; the greedy prefix up to T
+    depends only on cells at or below T) started at a quarter of the one-pass
+    threshold: it must raise T over further rounds and still report the exact
+    top-k, the same as the run that starts at the one-pass threshold."""
+    n, lo, hi, excl = 3000, 20, 40, 10
+    t = np.cumsum(np.random.default_rng(77).standard_normal(n))
+    if not _KSWEEP_ROWS:
+        _KSWEEP_ROWS.update(oracle.pan_profile(t, range(lo, hi + 1), excl))
+    base, st0 = run(gpu, ws, t, lo, hi, excl, precision=PRECS[prec])
+    dbg = gpu.Debug()
+    dbg.size = C.sizeof(gpu.Debug)
+    dbg.t_start_scale = 0.25
+    res, st = run(gpu, ws, t, lo, hi, excl, debug=dbg, precision=PRECS[prec])
+    print(f"{prec}: certify rounds {st0['certify_rounds']} -> {st['certify_rounds']}")
+    assert st["certify_rounds"] >= 2
+    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, 20, oracle, t)
+    assert ok, msg
+    assert res == base
+    dbg.t_start_scale = 1.5
+    with pytest.raises(gpu.PMPError) as e:
+        run(gpu, ws, t, lo, hi, excl, debug=dbg, precision=PRECS[prec])
+    assert e.value.code == gpu.PMP_EINVAL
+
+
 _MAXLEN_ROWS: dict = {}
 
 
