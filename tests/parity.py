@@ -29,12 +29,14 @@ def canonical_equal(gpu, ref) -> tuple[bool, str]:
     return True, ""
 
 
-def tie_aware_equal(gpu, rows, k: int, oracle, t=None) -> tuple[bool, str]:
+def tie_aware_equal(gpu, rows, k: int, oracle, t=None, *, excl: int) -> tuple[bool, str]:
     """Accept a GPU list that differs from the canonical one only inside tie
     groups: re-run the oracle's greedy with each tie group (P within 1e-9
     relative, or both 0) reordered to put the GPU's cells first; the accepted
-    list must equal the GPU's, and each GPU neighbour j must attain the
-    cell's exact minimum within the distance tolerance."""
+    list must equal the GPU's, and each GPU neighbour j that differs from the
+    oracle's must be a valid partner (|i - j| >= excl, the exclusion zone of
+    Sec. 2) attaining the cell's exact minimum within the distance
+    tolerance."""
     P, m, i, j = oracle.sorted_cells(rows)
     gpu_cells = {(g.m, g.i): x for x, g in enumerate(gpu)}
     order = np.arange(len(P))
@@ -57,19 +59,23 @@ def tie_aware_equal(gpu, rows, k: int, oracle, t=None) -> tuple[bool, str]:
         if g.j != a.j:
             if t is None:
                 return False, f"neighbour at {(g.i, g.m)}: gpu {g.j} oracle {a.j}"
+            if abs(g.i - g.j) < excl:
+                return False, f"gpu neighbour {g.j} of {(g.i, g.m)} lies in the exclusion zone"
             dj = oracle.snap(oracle.distance(t, g.m, g.i, g.j))
-            if abs(g.i - g.j) < 1 or not dist_close(dj, a.dist):
+            if not dist_close(dj, a.dist):
                 return False, f"gpu neighbour {g.j} of {(g.i, g.m)} is not a minimizer"
     return True, ""
 
 
-def check_topk(gpu, rows, k, oracle, t=None):
-    """Canonical equality, else the tie-aware acceptance test."""
+def check_topk(gpu, rows, k, oracle, t=None, *, excl: int):
+    """Canonical equality, else the tie-aware acceptance test (excl: the
+    request's exclusion zone, which every substituted neighbour must
+    respect)."""
     ref = oracle.topk(rows, k)
     ok, msg = canonical_equal(gpu, ref)
     if ok:
         return True, ""
-    ok2, msg2 = tie_aware_equal(gpu, rows, k, oracle, t)
+    ok2, msg2 = tie_aware_equal(gpu, rows, k, oracle, t, excl=excl)
     if not ok2:
         return False, msg + " | " + msg2
     return True, "tie-aware"

@@ -166,7 +166,7 @@ def test_random_walk_all_lengths_profile_certified(gpu, ws, oracle, prec):
     dbg.profile_final = pf.data_ptr()
     dbg.profile_pass = pp.data_ptr()
     res, st = run(gpu, ws, t, 12, 39, 9, 20, debug=dbg, m_step=3, precision=PRECS[prec])
-    ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+    ok, msg = parity.check_topk(res, rows, 20, oracle, t, excl=9)
     assert ok, msg
     T = st["threshold"]
     P_or = np.concatenate([rows[m][0] for m in lengths])
@@ -339,7 +339,7 @@ def test_result_independent_of_width_budget_seed_precision(gpu, ws, oracle):
                dict(signature_bits=8), dict(gamma=1), dict(probe_cap=0)]:
         for budget in (4, 16, 64):
             res, _ = run(gpu, ws, t, 40, 70, 40, budget=budget, m_step=5, **kw)
-            ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+            ok, msg = parity.check_topk(res, rows, 20, oracle, t, excl=40)
             assert ok, (kw, budget, msg)
             assert [(r.i, r.m) for r in res] == [(x.i, x.m) for x in ref]
 
@@ -377,7 +377,7 @@ def test_fewer_cells_than_k(gpu, ws, oracle):
     t = np.random.default_rng(2).standard_normal(140)
     rows = oracle.pan_profile(t, [30], 90)
     res, _ = run(gpu, ws, t, 30, 30, 90, k=50)
-    ok, msg = parity.check_topk(res, rows, 50, oracle, t)
+    ok, msg = parity.check_topk(res, rows, 50, oracle, t, excl=90)
     assert ok, msg
     assert 0 < len(res) < 50
 
@@ -390,7 +390,7 @@ def test_duplicates_and_flat_runs(gpu, ws, oracle):
     lengths = range(16, 31, 2)
     rows = oracle.pan_profile(t, lengths, 20)
     res, _ = run(gpu, ws, t, 16, 30, 20, m_step=2)
-    ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+    ok, msg = parity.check_topk(res, rows, 20, oracle, t, excl=20)
     assert ok, msg
     assert res[0].dist == 0.0
 
@@ -401,7 +401,7 @@ def test_ragged_and_extreme_lengths(gpu, ws, oracle, n, lo, hi, excl):
     t = np.cumsum(np.random.default_rng(n).standard_normal(n))
     rows = oracle.pan_profile(t, range(lo, hi + 1), excl)
     res, _ = run(gpu, ws, t, lo, hi, excl)
-    ok, msg = parity.check_topk(res, rows, 20, oracle, t)
+    ok, msg = parity.check_topk(res, rows, 20, oracle, t, excl=excl)
     assert ok, msg
 
 
@@ -421,7 +421,7 @@ def test_k_from_one_to_many(gpu, ws, oracle, prec, k):
         _KSWEEP_ROWS.update(oracle.pan_profile(t, range(lo, hi + 1), excl))
     res, st = run(gpu, ws, t, lo, hi, excl, k=k, precision=PRECS[prec])
     assert len(res) == k
-    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, k, oracle, t)
+    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, k, oracle, t, excl=excl)
     assert ok, msg
     print(f"k={k} {prec}: certify rounds {st['certify_rounds']}")
 
@@ -443,7 +443,7 @@ def test_threshold_loop_past_first_round(gpu, ws, oracle, prec):
     res, st = run(gpu, ws, t, lo, hi, excl, debug=dbg, precision=PRECS[prec])
     print(f"{prec}: certify rounds {st0['certify_rounds']} -> {st['certify_rounds']}")
     assert st["certify_rounds"] >= 2
-    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, 20, oracle, t)
+    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, 20, oracle, t, excl=excl)
     assert ok, msg
     assert res == base
     dbg.t_start_scale = 1.5
@@ -465,7 +465,7 @@ def test_longest_supported_windows(gpu, ws, oracle, prec):
     if not _MAXLEN_ROWS:
         _MAXLEN_ROWS.update(oracle.pan_profile(t, range(lo, hi + 1), excl))
     res, _ = run(gpu, ws, t, lo, hi, excl, precision=PRECS[prec])
-    ok, msg = parity.check_topk(res, _MAXLEN_ROWS, 20, oracle, t)
+    ok, msg = parity.check_topk(res, _MAXLEN_ROWS, 20, oracle, t, excl=excl)
     assert ok, msg
 
 
