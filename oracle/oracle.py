@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+            "gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
             "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
             "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
@@ -58,6 +58,7 @@ def lib():
         L.orc_distance.restype = d
         L.orc_profile.argtypes = [P, i64, i32, i32, P, P]
         L.orc_cells.argtypes = [P, i64, i32, i32, P, i64, i32, P, P]
+        L.orc_profile_v2.argtypes = [P, i64, i32, i32, d, P, P, P, P]
         L.orc_kprime.argtypes = [i32, i32]
         L.orc_kprime.restype = i32
         L.orc_features.argtypes = [P, i64, i32, i64, i32, P]
@@ -108,6 +109,34 @@ def profile(t, m: int, excl: int):
     if lib().orc_profile(_ptr(t), len(t), m, excl, _ptr(P), _ptr(I)) != 0:
         raise ValueError("bad profile arguments")
     return P, I
+
+
+def profile_v2(t, m: int, excl: int, band_scale: float = 1.0, audit: bool = False):
+    """Oracle v2: the same exact (P_m, I_m) as ``profile``, from the
+    closed-form screen with a rigorous rounding band (see pmp_oracle.c).
+    Returns (P, I, direct distances computed, largest band ratio or None);
+    with ``audit`` every pair is also checked against the band (slow)."""
+    t = _f64(t)
+    W = len(t) - m + 1
+    P = np.empty(W)
+    I = np.empty(W, dtype=np.int64)
+    nd = C.c_int64(0)
+    aud = C.c_double(0.0)
+    if lib().orc_profile_v2(_ptr(t), len(t), m, excl, float(band_scale), _ptr(P), _ptr(I),
+                            C.byref(nd), C.byref(aud) if audit else None) != 0:
+        raise ValueError("bad profile arguments")
+    return P, I, int(nd.value), (float(aud.value) if audit else None)
+
+
+def pan_profile_v2(t, lengths, excl: int, progress=None):
+    """Oracle v2 rows for every listed length: {m: (P_m, I_m)}."""
+    out = {}
+    for m in lengths:
+        P, I, nd, _ = profile_v2(t, int(m), excl)
+        out[int(m)] = (P, I)
+        if progress:
+            progress(int(m), nd)
+    return out
 
 
 def cells(t, m: int, excl: int, starts, stop_at_zero: bool = False):

@@ -61,11 +61,32 @@ def ecg_small():
           top, time.time() - t0)
 
 
+def ecg_1m():
+    """The ECG-like workload at full size (1M samples, 51 lengths) by oracle
+    v2: every row exact, equal to v1's by construction (the screen only
+    chooses which pairs the direct formula recomputes)."""
+    n, seed = 1_000_000, synth.SEED_ECG_1M
+    t = synth.ecg_like(n, seed)
+    t0 = time.time()
+
+    def progress(m, nd):
+        print(f"  m={m} done, {nd} direct distances, {time.time() - t0:.0f} s", flush=True)
+
+    rows = O.pan_profile_v2(t, range(100, 401, 6), 100, progress=progress)
+    top = O.topk(rows, 20)
+    _dump("ecg1m_top20", dict(workload="ecg-like", generator="ecg_like", n=n, seed=seed,
+                              m_min=100, m_max=400, m_step=6, exclusion=100, k=20,
+                              method="oracle v2 (closed-form screen with a rigorous band, "
+                                     "direct recomputation), every length"),
+          top, time.time() - t0)
+
+
 JOBS = {
     "tiny": tiny,
     "wafer100k": lambda: wafer(100_000, synth.SEED_WAFER_100K, "wafer100k_top20"),
     "wafer5m": lambda: wafer(5_000_000, synth.SEED_WAFER_5M, "wafer5m_top20"),
     "ecg5k": ecg_small,
+    "ecg1m": ecg_1m,
 }
 
 if __name__ == "__main__":
