@@ -130,13 +130,19 @@ int pmp_open_ex(const double *series, int64_t n, int32_t m_min, int32_t m_max,
                 const pmp_options *opt, pmp_motif *out, int32_t *n_out,
                 pmp_stats *stats);
 
-/* Upper bound of the device workspace pmp_run_device needs. */
-size_t pmp_workspace_bytes(int64_t n, int32_t m_min, int32_t m_max,
+/* Upper bound of the device workspace pmp_run_device needs for a request
+ * of these sizes, k reported motifs and any budget >= 1 (the deepest
+ * directories, budget 1, bound every other budget).  The selection buffers
+ * grow with k (k (m_max + 1) cells of the upper profile are selected, Sec. 2
+ * top-k rule), so the bound depends on it.  0 on invalid arguments (the
+ * checks of pmp_open on n, m_min, m_max and k, and on the options). */
+size_t pmp_workspace_bytes(int64_t n, int32_t m_min, int32_t m_max, int32_t k,
                            const pmp_options *opt);
 
 /* Device-resident form: d_series is a device pointer (FP64, n samples) on the
  * current HIP device; d_workspace/ws_bytes a caller-owned device buffer of at
- * least pmp_workspace_bytes() bytes (256-byte aligned); stream a hipStream_t
+ * least pmp_workspace_bytes(n, m_min, m_max, k, opt) bytes (256-byte
+ * aligned; PMP_ENOMEM if smaller than the request needs); stream a hipStream_t
  * (NULL = default stream).  All work is enqueued on that stream; the call
  * returns after the results are in `out` (host memory).  The library
  * allocates no device memory in this form. */

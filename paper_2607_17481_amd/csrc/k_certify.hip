@@ -22,13 +22,35 @@ namespace pmp {
 
 // ---------------------------------------------------------------- select
 
+// The radix select runs on the device from start to end: six passes of a
+// histogram over 11 (the last 9) bits of the FP64 bit pattern, each followed
+// by one block that picks the bin holding the `remaining`-th smallest value
+// and narrows the prefix `high`.  The state lives in a SelState; the host
+// reads it once, with the selected cells.
+
+// Start state: every finite value is a candidate, the histogram is clear.
+__global__ void k_select_init(SelState *__restrict__ st, int64_t need,
+                              unsigned int *__restrict__ hist) {
+    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) hist[i] = 0;
+    if (threadIdx.x == 0) {
+        st->high = 0;
+        st->pivot = kInfBits;
+        st->remaining = need;
+        st->need_eq = 0;
+        st->nless = 0;
+        st->done = 0;
+    }
+}
+
 // Histogram of bits [shift, shift + nbits) of P over cells whose bits above
-// shift + nbits equal `high`.
+// shift + nbits equal the state's prefix.
 __global__ __launch_bounds__(kBlock) void k_select_hist(const uint64_t *__restrict__ P,
                                                         int64_t n, int shift, int nbits,
-                                                        uint64_t high,
+                                                        const SelState *__restrict__ st,
                                                         unsigned int *__restrict__ hist) {
-    __shared__ unsigned int h[2048];
+    if (st->done) return;
+    const uint64_t high = st->high;
+    __shared__ unsigned int h[kSelBins];
     for (int i = threadIdx.x; i < (1 << nbits); i += kBlock) h[i] = 0;
     __syncthreads();
     const int top = shift + nbits;
@@ -44,13 +66,80 @@ __global__ __launch_bounds__(kBlock) void k_select_hist(const uint64_t *__restri
         if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
+// One block of kBlock threads: the bin of the remaining-th value, then the
+// histogram is cleared for the next pass.  Pass 0 also settles two cases:
+// fewer finite values than wanted (take them all), and a first bin of 0,
+// whose values are exact zeros (the snap leaves nothing between 0 and 1e-6).
+__global__ __launch_bounds__(kBlock) void k_select_pick(unsigned int *__restrict__ hist,
+                                                        int nbits, int pass, int last,
+                                                        SelState *__restrict__ st) {
+    __shared__ unsigned long long part[kBlock];
+    constexpr int kPer = kSelBins / kBlock;
+    const int nb = 1 << nbits;
+    const int done = st->done;
+    unsigned long long mine = 0;
+    unsigned int hv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = threadIdx.x * kPer + u;
+        hv[u] = (!done && b < nb) ? hist[b] : 0u;
+        mine += hv[u];
+    }
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    // inclusive scan of the per-thread sums (Hillis-Steele)
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const unsigned long long x = threadIdx.x >= off ? part[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    if (!done) {
+        const unsigned long long total = part[kBlock - 1];
+        const unsigned long long rem = (unsigned long long)st->remaining;
+        if (pass == 0 && total < rem) {
+            if (threadIdx.x == 0) {          // fewer finite cells than needed: take all
+                st->pivot = kInfBits;
+                st->need_eq = 0;
+                st->done = 1;
+            }
+        } else {
+            unsigned long long cum = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+            if (cum < rem && part[threadIdx.x] >= rem) {   // exactly one thread
+                int bin = threadIdx.x * kPer;
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    if (cum + hv[u] >= rem) { bin = threadIdx.x * kPer + u; break; }
+                    cum += hv[u];
+                }
+                const unsigned long long r2 = rem - cum;
+                const uint64_t high = (st->high << nbits) | (uint64_t)bin;
+                st->remaining = (int64_t)r2;
+                st->high = high;
+                if (pass == 0 && bin == 0) {
+                    st->pivot = 0;
+                    st->need_eq = (int64_t)r2;
+                    st->done = 1;
+                } else if (last) {
+                    st->pivot = high;
+                    st->need_eq = (int64_t)r2;
+                    st->done = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSelBins; i += kBlock) hist[i] = 0;
+}
+
 // Per-block counts of cells equal to the pivot (for the ordered compaction).
 constexpr int kSelTile = kBlock * 16;
 
 __global__ __launch_bounds__(kBlock) void k_select_count(const uint64_t *__restrict__ P, int64_t n,
-                                                         uint64_t pivot,
+                                                         const SelState *__restrict__ st,
                                                          uint32_t *__restrict__ cnt) {
     __shared__ uint32_t wc[kBlock / kWave];
+    const uint64_t pivot = st->pivot;
     int64_t base = (int64_t)blockIdx.x * kSelTile;
     uint32_t c = 0;
     for (int r = 0; r < 16; ++r) {
@@ -70,13 +159,16 @@ __global__ __launch_bounds__(kBlock) void k_select_count(const uint64_t *__restr
 // Cells below the pivot are appended (any order); cells equal to the pivot are
 // written in natural order up to `need` of them.
 __global__ __launch_bounds__(kBlock) void k_select_emit(const uint64_t *__restrict__ P, int64_t n,
-                                                        uint64_t pivot, uint32_t need,
+                                                        SelState *__restrict__ st,
                                                         const uint32_t *__restrict__ off,
                                                         uint32_t *__restrict__ less,
                                                         uint64_t *__restrict__ less_val,
-                                                        uint32_t *__restrict__ nless, uint32_t cap,
+                                                        uint32_t cap,
                                                         uint32_t *__restrict__ eq) {
     __shared__ uint32_t wc[kBlock / kWave];
+    const uint64_t pivot = st->pivot;
+    const uint32_t need = (uint32_t)st->need_eq;
+    uint32_t *nless = &st->nless;
     int64_t base = (int64_t)blockIdx.x * kSelTile;
     uint32_t run = off[blockIdx.x];
     if (run >= need) {
@@ -162,6 +254,21 @@ __global__ __launch_bounds__(kBlock) void k_rows(Req q, const RowReq *__restrict
     }
 }
 
+// Cells of the selected positions: the first min(nless, cap) of `less` and
+// the first need_eq of `eq`.
+__global__ __launch_bounds__(kBlock) void k_select_cells(const uint32_t *__restrict__ cell,
+                                                         const SelState *__restrict__ st,
+                                                         const uint32_t *__restrict__ less,
+                                                         const uint32_t *__restrict__ eq,
+                                                         int64_t cap, uint32_t *__restrict__ less_cell,
+                                                         uint32_t *__restrict__ eq_cell) {
+    const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (x >= cap) return;
+    const int64_t nl = (int64_t)st->nless < cap ? (int64_t)st->nless : cap;
+    if (x < nl) less_cell[x] = cell[less[x]];
+    if (x < st->need_eq) eq_cell[x] = cell[eq[x]];
+}
+
 // out[x] = src[idx[x]]
 __global__ __launch_bounds__(kBlock) void k_gather_u32(const uint32_t *__restrict__ src,
                                                        const uint32_t *__restrict__ idx, int64_t n,
@@ -179,6 +286,13 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t *__restrict__ p, i
         p[i] = v;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ p, int64_t n,
+                                                     uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -188,25 +302,31 @@ static inline unsigned gridcap(int64_t n, int64_t cap) {
     return (unsigned)(b < cap ? b : cap);
 }
 
-void launch_select_hist(const uint64_t *P, int64_t n, int shift, int nbits, uint64_t high,
-                        unsigned int *hist, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_hist, dim3(gridcap(n, 4096)), dim3(kBlock), 0, s, P, n, shift,
-                       nbits, high, hist);
-}
-
 int64_t select_blocks(int64_t n) { return (n + kSelTile - 1) / kSelTile; }
 
-void launch_select_count(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t *cnt,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_select_count, dim3((unsigned)select_blocks(n)), dim3(kBlock), 0, s, P, n,
-                       pivot, cnt);
-}
-
-void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t need,
-                        const uint32_t *off, uint32_t *less, uint64_t *less_val, uint32_t *nless,
-                        uint32_t cap, uint32_t *eq, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_emit, dim3((unsigned)select_blocks(n)), dim3(kBlock), 0, s, P, n,
-                       pivot, need, off, less, less_val, nless, cap, eq);
+void launch_select(const uint64_t *P, int64_t n, int64_t need, SelState *st,
+                   unsigned int *hist, uint32_t *cnt, uint32_t *scan_tmp, uint32_t *less,
+                   uint64_t *less_val, uint32_t *eq, uint32_t *less_cell, uint32_t *eq_cell,
+                   const uint32_t *cell, hipStream_t s) {
+    static const int shifts[6] = {53, 42, 31, 20, 9, 0};
+    static const int widths[6] = {11, 11, 11, 11, 11, 9};
+    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(kBlock), 0, s, st, need, hist);
+    if (n <= 0) return;
+    for (int ps = 0; ps < 6; ++ps) {
+        hipLaunchKernelGGL(k_select_hist, dim3(gridcap(n, 4096)), dim3(kBlock), 0, s, P, n,
+                           shifts[ps], widths[ps], (const SelState *)st, hist);
+        hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(kBlock), 0, s, hist, widths[ps], ps,
+                           ps == 5 ? 1 : 0, st);
+    }
+    const int64_t nsb = select_blocks(n);
+    hipLaunchKernelGGL(k_select_count, dim3((unsigned)nsb), dim3(kBlock), 0, s, P, n,
+                       (const SelState *)st, cnt);
+    scan_exclusive_u32(cnt, cnt, nsb, nullptr, scan_tmp, s);
+    hipLaunchKernelGGL(k_select_emit, dim3((unsigned)nsb), dim3(kBlock), 0, s, P, n, st,
+                       (const uint32_t *)cnt, less, less_val, (uint32_t)need, eq);
+    hipLaunchKernelGGL(k_select_cells, dim3(nblk(need)), dim3(kBlock), 0, s, cell,
+                       (const SelState *)st, (const uint32_t *)less, (const uint32_t *)eq, need,
+                       less_cell, eq_cell);
 }
 
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
@@ -224,6 +344,11 @@ void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL(k_fill_u64, dim3(gridcap(n, 8192)), dim3(kBlock), 0, s, p, n, v);
+}
+
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill_u32, dim3(gridcap(n, 8192)), dim3(kBlock), 0, s, p, n, v);
 }
 
 }  // namespace pmp

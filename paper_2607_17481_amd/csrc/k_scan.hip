@@ -255,7 +255,7 @@ size_t scan_temp_bytes(int64_t n) {
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total,
                         void *temp, hipStream_t s) {
     if (n <= 0) {
-        if (total) (void)hipMemsetAsync(total, 0, sizeof(uint32_t), s);
+        if (total) launch_fill_u32(total, 1, 0u, s);
         return;
     }
     int64_t nb = cdiv(n, kScanTile);

@@ -136,6 +136,17 @@ struct GridLen {
     float rp;             // bound on any coordinate difference of a pair within R_f
 };
 
+// State of the device-side radix select (k_certify.hip).
+constexpr int kSelBins = 2048;            // bins of one select pass (11 bits)
+struct SelState {
+    uint64_t high;        // bits of the selected prefix so far
+    uint64_t pivot;       // FP64 bits of the boundary value (kInfBits: take all)
+    int64_t remaining;    // values still wanted at or below the prefix
+    int64_t need_eq;      // values equal to the pivot to take, in cell order
+    uint32_t nless;       // values below the pivot found by the emit pass
+    int32_t done;         // the pivot is known
+};
+
 struct RowReq {
     int32_t l;          // length index
     int32_t pad;
@@ -423,14 +434,16 @@ void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,
                         hipStream_t s);
 // (k_certify.hip)
-void launch_select_hist(const uint64_t *P, int64_t n, int shift, int nbits, uint64_t high,
-                        unsigned int *hist, hipStream_t s);
 int64_t select_blocks(int64_t n);
-void launch_select_count(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t *cnt,
-                         hipStream_t s);
-void launch_select_emit(const uint64_t *P, int64_t n, uint64_t pivot, uint32_t need,
-                        const uint32_t *off, uint32_t *less, uint64_t *less_val, uint32_t *nless,
-                        uint32_t cap, uint32_t *eq, hipStream_t s);
+// The first `need` values of P in (value, position) order: positions below the
+// pivot go to less (unordered, with their values in less_val), positions
+// equal to it to eq (position order); less_cell / eq_cell hold cell[position].
+// Everything runs on the stream; st holds the counts when the stream reaches
+// the end.
+void launch_select(const uint64_t *P, int64_t n, int64_t need, SelState *st,
+                   unsigned int *hist, uint32_t *cnt, uint32_t *scan_tmp, uint32_t *less,
+                   uint64_t *less_val, uint32_t *eq, uint32_t *less_cell, uint32_t *eq_cell,
+                   const uint32_t *cell, hipStream_t s);
 // (k_join.hip)
 size_t join_cov_doubles(int L);
 // principal directions: covariance of a sample, then power iteration (GPU)
@@ -446,6 +459,7 @@ void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uin
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,
                        hipStream_t s);
 

@@ -383,7 +383,6 @@ struct Bufs {
     int64_t *bbase;            // MFMA sketch basis: offsets per length, then hi / mid / lo tables
     uint16_t *bh, *bm, *bl;
     unsigned int *hist;
-    uint32_t *nless;
     RowReq *rows;
     unsigned long long *row_min, *row_arg;
     int64_t *cal_starts;
@@ -400,11 +399,18 @@ struct Bufs {
     uint32_t *skey, *sval, *skey2, *sval2, *pcell, *bstart;
     void *sort_tmp;
     uint32_t *jk, *jv, *jk2, *jv2;
-    uint32_t *sel_cnt, *less_k, *eq_k, *sel_cell;
+    uint32_t *sel_cnt;
+    // the selection's results, one contiguous block read back at once:
+    // state, then less_val, less_k, less_cell, eq_k, eq_cell (need each)
+    char *selblk;
+    SelState *sel;
     uint64_t *less_val;
+    uint32_t *less_k, *less_cell, *eq_k, *eq_cell;
 };
 
 static int64_t need_select(int k, int m_max) { return (int64_t)k * (m_max + 1); }
+constexpr size_t kSelHead = 256;          // SelState, padded
+static size_t select_block_bytes(int64_t need) { return kSelHead + (size_t)need * 24; }
 
 static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.len = take<LenInfo>(a, p.L);
@@ -428,8 +434,7 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
         b.bl = take<uint16_t>(a, ne);
     }
     b.gl = take<GridLen>(a, p.L);
-    b.hist = take<unsigned int>(a, 2048);
-    b.nless = take<uint32_t>(a, 1);
+    b.hist = take<unsigned int>(a, kSelBins);
     b.rows = take<RowReq>(a, k);
     b.row_min = take<unsigned long long>(a, k);
     b.row_arg = take<unsigned long long>(a, k);
@@ -462,10 +467,13 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
     b.jk2 = take<uint32_t>(a, N);
     b.jv2 = take<uint32_t>(a, N);
     b.sel_cnt = take<uint32_t>(a, select_blocks(N) + 1);
-    b.less_k = take<uint32_t>(a, need);
-    b.less_val = take<uint64_t>(a, need);
-    b.eq_k = take<uint32_t>(a, need);
-    b.sel_cell = take<uint32_t>(a, 2 * need);
+    b.selblk = (char *)a.take(select_block_bytes(need));
+    b.sel = (SelState *)b.selblk;
+    b.less_val = (uint64_t *)(b.selblk + kSelHead);
+    b.less_k = (uint32_t *)(b.less_val + need);
+    b.less_cell = b.less_k + need;
+    b.eq_k = b.less_cell + need;
+    b.eq_cell = b.eq_k + need;
 }
 
 // ------------------------------------------------------------ selection
@@ -495,76 +503,35 @@ static int len_of_cell(const Plan &p, int64_t cell) {
 // The first `need` cells of the (P, m, i) order, sorted, then the greedy of
 // Sec. 2 over them.  P is indexed by k, whose order is the (m, i) order of the
 // non-constant windows; constant windows have no cell value.
+// The selection runs on the device (launch_select); one read-back brings the
+// state and the selected positions, values and cells, after any copies the
+// caller has already enqueued on the stream (they complete with the same
+// synchronization).
 static int select_topk(const Plan &p, Bufs &b, int k, hipStream_t s, std::vector<Cand> &accepted) {
     accepted.clear();
-    const uint64_t *dP = b.P;
     const int64_t N = p.N;
     const int64_t need_all = need_select(k, p.max_m);
-    const int shifts[6] = {53, 42, 31, 20, 9, 0};
-    const int widths[6] = {11, 11, 11, 11, 11, 9};
-    uint64_t high = 0;
-    int64_t remaining = need_all;
-    uint64_t pivot = kInfBits;
-    int64_t need_eq = 0;
-    std::vector<unsigned int> h(2048);
-    for (int ps = 0; ps < 6 && N > 0; ++ps) {
-        HIPCHK(hipMemsetAsync(b.hist, 0, 2048 * sizeof(unsigned int), s));
-        launch_select_hist(dP, N, shifts[ps], widths[ps], high, b.hist, s);
-        HIPCHK(hipMemcpyAsync(h.data(), b.hist, (1 << widths[ps]) * sizeof(unsigned int),
-                              hipMemcpyDeviceToHost, s));
+    if (N == 0) {
         HIPCHK(hipStreamSynchronize(s));
-        int64_t tot = 0;
-        for (int i = 0; i < (1 << widths[ps]); ++i) tot += h[i];
-        if (ps == 0 && tot < remaining) {   // fewer finite cells than needed: take all
-            pivot = kInfBits;
-            need_eq = 0;
-            break;
-        }
-        int64_t cum = 0;
-        int bin = -1;
-        for (int i = 0; i < (1 << widths[ps]); ++i) {
-            if (cum + h[i] >= remaining) { bin = i; break; }
-            cum += h[i];
-        }
-        remaining -= cum;
-        high = (high << widths[ps]) | (uint64_t)bin;
-        if (ps == 0 && bin == 0) {           // exponent field 0: only exact zeros
-            pivot = 0;
-            need_eq = remaining;
-            break;
-        }
-        if (ps == 5) {
-            pivot = high;
-            need_eq = remaining;
-        }
+        return PMP_OK;
     }
-    if (N == 0) return PMP_OK;
-    // ordered compaction
-    const int64_t nsb = select_blocks(N);
-    launch_select_count(dP, N, pivot, b.sel_cnt, s);
-    scan_exclusive_u32(b.sel_cnt, b.sel_cnt, nsb, nullptr, b.scan_tmp, s);
-    HIPCHK(hipMemsetAsync(b.nless, 0, sizeof(uint32_t), s));
-    launch_select_emit(dP, N, pivot, (uint32_t)need_eq, b.sel_cnt, b.less_k, b.less_val, b.nless,
-                       (uint32_t)need_all, b.eq_k, s);
-    uint32_t nless = 0;
-    HIPCHK(hipMemcpyAsync(&nless, b.nless, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    launch_select(b.P, N, need_all, b.sel, b.hist, b.sel_cnt, b.scan_tmp, b.less_k, b.less_val,
+                  b.eq_k, b.less_cell, b.eq_cell, b.cell, s);
+    std::vector<char> host(select_block_bytes(need_all));
+    HIPCHK(hipMemcpyAsync(host.data(), b.selblk, host.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (nless > (uint32_t)need_all) return fail(PMP_EINTERNAL, "selection overflow");
-    // cells of the selected positions
-    launch_gather_u32(b.cell, b.less_k, nless, b.sel_cell, s);
-    launch_gather_u32(b.cell, b.eq_k, need_eq, b.sel_cell + need_all, s);
-    std::vector<uint32_t> lk(nless), ek(need_eq), lc(nless), ec(need_eq);
-    std::vector<uint64_t> lv(nless);
-    if (nless) {
-        HIPCHK(hipMemcpyAsync(lk.data(), b.less_k, nless * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(lv.data(), b.less_val, nless * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(lc.data(), b.sel_cell, nless * 4, hipMemcpyDeviceToHost, s));
-    }
-    if (need_eq) {
-        HIPCHK(hipMemcpyAsync(ek.data(), b.eq_k, need_eq * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(ec.data(), b.sel_cell + need_all, need_eq * 4, hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
+    SelState st;
+    memcpy(&st, host.data(), sizeof(st));
+    if (!st.done) return fail(PMP_EINTERNAL, "selection did not settle");
+    if (st.nless > (uint32_t)need_all) return fail(PMP_EINTERNAL, "selection overflow");
+    const uint32_t nless = st.nless;
+    const int64_t need_eq = st.need_eq;
+    const uint64_t pivot = st.pivot;
+    const uint64_t *lv = (const uint64_t *)(host.data() + kSelHead);
+    const uint32_t *lk = (const uint32_t *)(lv + need_all);
+    const uint32_t *lc = lk + need_all;
+    const uint32_t *ek = lc + need_all;
+    const uint32_t *ec = ek + need_all;
     std::vector<Cand> c;
     c.reserve(nless + need_eq);
     for (uint32_t x = 0; x < nless; ++x) {
@@ -595,16 +562,20 @@ static int select_topk(const Plan &p, Bufs &b, int k, hipStream_t s, std::vector
 
 // ------------------------------------------------------------- pipeline
 
+// Phase times from HIP events on the request's stream.  Off (no events
+// created at all) for callers that must not allocate.
 struct Timer {
-    hipEvent_t ev[8];
+    hipEvent_t ev[8] = {};
     bool ok = false;
-    Timer() {
+    explicit Timer(bool on) {
+        if (!on) return;
         ok = true;
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) ok = false;
     }
     ~Timer() {
-        for (auto &e : ev) (void)hipEventDestroy(e);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
     void mark(int i, hipStream_t s) {
         if (ok) (void)hipEventRecord(ev[i], s);
@@ -651,6 +622,7 @@ struct Run {
     int32_t *n_out;
     pmp_stats *st;
     pmp_debug *dbg;
+    bool timed = true;     // phase events (stats); off for the no-allocation entry
 };
 
 // debug exports: per-k arrays to per-cell arrays (constant cells keep the fill)
@@ -692,16 +664,16 @@ static int run_pipeline(Run &R, Arena &ar) {
     Bufs b;
     carve1(ar, b, p, R.k);
     if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
-    Timer tm;
+    Timer tm(R.timed && R.st);
     tm.mark(0, s);
 
     // ---- validation, change points, index counts per tile
-    HIPCHK(hipMemsetAsync(b.bad, 0, sizeof(int), s));
+    launch_fill_u32((uint32_t *)b.bad, 1, 0u, s);
     launch_changepoints(R.t, R.n, b.flags, b.bad, s);
     scan_exclusive_u32(b.flags, b.E, R.n + 1, nullptr, b.scan_tmp, s);
     HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
     launch_tile_counts(b.len, p.L, b.E, p.ntiles, b.tile_off, s);
-    HIPCHK(hipMemsetAsync(b.tile_off + p.ntiles, 0, sizeof(uint32_t), s));
+    launch_fill_u32(b.tile_off + p.ntiles, 1, 0u, s);
     scan_exclusive_u32(b.tile_off, b.tile_off, p.ntiles + 1, nullptr, b.scan_tmp, s);
     int bad = 0;
     std::vector<uint32_t> toff(p.ntiles + 1);
@@ -712,6 +684,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     std::vector<int> cal_m;
     std::vector<std::vector<int64_t>> cal_st;
     std::vector<int64_t> cal_all(3 * 256, 0);   // lives until the sync below
+    std::vector<double> cal_host;
     if (o.K == 0) {
         int idx[3] = {0, (p.L - 1) / 2, p.L - 1};
         for (int a = 0; a < 3; ++a) {
@@ -728,17 +701,18 @@ static int run_pipeline(Run &R, Arena &ar) {
                                R.t, (const int64_t *)b.cal_starts + a * 256,
                                (int)cal_st[a].size(), cal_m[a],
                                b.cal_win + (int64_t)a * 256 * p.max_m);
+        cal_host.resize((size_t)3 * 256 * p.max_m);
+        HIPCHK(hipMemcpyAsync(cal_host.data(), b.cal_win, cal_host.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     if (bad) return fail(PMP_EINVAL, "series contains a non-finite sample");
     int K = o.K;
     if (K == 0) {
         std::vector<std::vector<std::vector<double>>> sets(cal_m.size());
-        std::vector<double> host((size_t)3 * 256 * p.max_m);
-        HIPCHK(hipMemcpy(host.data(), b.cal_win, host.size() * sizeof(double), hipMemcpyDeviceToHost));
         for (size_t a = 0; a < cal_m.size(); ++a)
             for (size_t w = 0; w < cal_st[a].size(); ++w) {
-                const double *src = host.data() + (a * 256 + w) * p.max_m;
+                const double *src = cal_host.data() + (a * 256 + w) * p.max_m;
                 sets[a].emplace_back(src, src + cal_m[a]);
             }
         K = calibrate(sets, cal_m, R.n, R.budget, o.gamma, o.B);
@@ -754,20 +728,23 @@ static int run_pipeline(Run &R, Arena &ar) {
     if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
     const int64_t N = p.N;
 
-    // ---- per-request constants
+    // ---- per-request constants (the host vectors live until the next
+    // synchronization, at the first selection)
+    std::vector<float> gproj_host((size_t)p.L * o.B * kFD);
     {
-        std::vector<float> g((size_t)p.L * o.B * kFD);
         std::vector<float> one((size_t)kMaxBits * kFD);
         for (int l = 0; l < p.L; ++l) {
             projections(o.seed, p.ms[l], one.data());
-            std::memcpy(g.data() + (size_t)l * o.B * kFD, one.data(), (size_t)o.B * kFD * sizeof(float));
+            std::memcpy(gproj_host.data() + (size_t)l * o.B * kFD, one.data(),
+                        (size_t)o.B * kFD * sizeof(float));
         }
-        HIPCHK(hipMemcpyAsync(b.gproj, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(b.len, p.len.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));   // host vectors above go out of scope
     }
-    HIPCHK(hipMemsetAsync(b.emax, 0, p.L * sizeof(float), s));
-    HIPCHK(hipMemsetAsync(b.counters, 0, C_NCOUNTERS * sizeof(unsigned long long), s));
+    HIPCHK(hipMemcpyAsync(b.gproj, gproj_host.data(), gproj_host.size() * sizeof(float),
+                          hipMemcpyHostToDevice, s));
+    const std::vector<LenInfo> len_host = p.len;
+    HIPCHK(hipMemcpyAsync(b.len, len_host.data(), p.L * sizeof(LenInfo), hipMemcpyHostToDevice, s));
+    launch_fill_u32((uint32_t *)b.emax, p.L, 0u, s);
+    launch_fill_u64((uint64_t *)b.counters, C_NCOUNTERS, 0ull, s);
 
     Req q{};
     q.t = R.t;
@@ -832,9 +809,6 @@ static int run_pipeline(Run &R, Arena &ar) {
     launch_probe(o.precision, q, b.bstart, N, p.max_m, s);
     tm.mark(5, s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
 
     if (R.dbg && R.dbg->profile_pass) {
         launch_fill_u64((uint64_t *)R.dbg->profile_pass, p.cells, kInfBits, s);
@@ -843,17 +817,19 @@ static int run_pipeline(Run &R, Arena &ar) {
                                b.cell, N, b.P, 0, (uint64_t *)R.dbg->profile_pass);
     }
 
-    // ---- selection on the upper profile
+    // ---- selection on the upper profile; the flag of unrepresentable
+    // windows and the largest feature errors come back with it
+    std::vector<float> emax(p.L);
+    HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
     std::vector<Cand> acc;
     int rc = select_topk(p, b, R.k, s, acc);
     if (rc) return rc;
+    if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
     if (R.dbg && R.dbg->t_start_scale > 0.0 && std::isfinite(T)) T *= R.dbg->t_start_scale;
     if (o.certify && N > 0) {
-        std::vector<float> emax(p.L);
-        HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
         std::vector<GridLen> gl(p.L);
         int64_t ntiles = 0;
         for (int l = 0; l < p.L; ++l) {
@@ -928,8 +904,7 @@ static int run_pipeline(Run &R, Arena &ar) {
             launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntiles,
                               cb1, cb2, cb3, Teff, s);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipStreamSynchronize(s));   // gl is rewritten next round
-            rc = select_topk(p, b, R.k, s, acc);
+            rc = select_topk(p, b, R.k, s, acc);   // synchronizes: gl may be rewritten next
             if (rc) return rc;
             if (std::isinf(T)) break;                               // exhaustive
             if (acc.size() == (size_t)R.k && acc.back().d <= T) break;
@@ -952,6 +927,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         memcpy(&rr[x].target, &d, 8);
     }
     std::vector<unsigned long long> rmin(nacc), rarg(nacc);
+    std::vector<unsigned long long> ctr(C_NCOUNTERS);
     if (nacc) {
         HIPCHK(hipMemcpyAsync(b.rows, rr.data(), nacc * sizeof(RowReq), hipMemcpyHostToDevice, s));
         launch_fill_u64((uint64_t *)b.row_min, nacc, kInfBits, s);
@@ -961,7 +937,13 @@ static int run_pipeline(Run &R, Arena &ar) {
         launch_rows(q, b.rows, nacc, maxN, b.row_min, b.row_arg, s);
         HIPCHK(hipMemcpyAsync(rmin.data(), b.row_min, nacc * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(rarg.data(), b.row_arg, nacc * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+    }
+    tm.mark(7, s);
+    if (R.st)
+        HIPCHK(hipMemcpyAsync(ctr.data(), b.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    if (nacc) {
         if (o.certify) {
             for (int x = 0; x < nacc; ++x)
                 if (rmin[x] != rr[x].target) {
@@ -975,9 +957,6 @@ static int run_pipeline(Run &R, Arena &ar) {
                 }
         }
     }
-    tm.mark(7, s);
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipGetLastError());
     for (int x = 0; x < nacc; ++x) {
         R.out[x].i = acc[x].i;
         R.out[x].j = (int64_t)rarg[x];
@@ -997,12 +976,12 @@ static int run_pipeline(Run &R, Arena &ar) {
         }
         const unsigned gb = (unsigned)((std::max<int64_t>(N, 1) + 255) / 256);
         if (d->mu) {
-            HIPCHK(hipMemsetAsync(d->mu, 0, p.cells * 8, s));
+            launch_fill_u64((uint64_t *)d->mu, p.cells, 0ull, s);
             if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N,
                                       (const uint64_t *)b.mu, 0, (uint64_t *)d->mu);
         }
         if (d->sigma) {
-            HIPCHK(hipMemsetAsync(d->sigma, 0, p.cells * 8, s));
+            launch_fill_u64((uint64_t *)d->sigma, p.cells, 0ull, s);
             if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N,
                                       (const uint64_t *)b.isig, 1, (uint64_t *)d->sigma);
         }
@@ -1023,7 +1002,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                                   hipMemcpyDeviceToDevice, s));
         if (d->features) {
             const size_t fb = (size_t)p.cells * kRec * (o.precision == 0 ? 8 : 4);
-            HIPCHK(hipMemsetAsync(d->features, 0, fb, s));
+            launch_fill_u32((uint32_t *)d->features, (int64_t)(fb / 4), 0u, s);
             const unsigned fbk = (unsigned)((std::max<int64_t>(N, 1) + 7) / 8);
             if (N && o.precision == 0)
                 hipLaunchKernelGGL(k_debug_features<double>, dim3(fbk), dim3(256), 0, s,
@@ -1037,8 +1016,6 @@ static int run_pipeline(Run &R, Arena &ar) {
 
     if (R.st) {
         pmp_stats *st = R.st;
-        std::vector<unsigned long long> ctr(C_NCOUNTERS);
-        HIPCHK(hipMemcpy(ctr.data(), b.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost));
         st->K = K;
         st->lengths = p.L;
         st->certify_rounds = rounds;
@@ -1128,11 +1105,12 @@ void pmp_default_options(pmp_options *o) {
 
 const char *pmp_last_error(void) { return g_err.c_str(); }
 
-size_t pmp_workspace_bytes(int64_t n, int32_t m_min, int32_t m_max, const pmp_options *opt) {
+size_t pmp_workspace_bytes(int64_t n, int32_t m_min, int32_t m_max, int32_t k,
+                           const pmp_options *opt) {
     Opt o;
     if (read_options(opt, o)) return 0;
-    if (check_args(n, m_min, m_max, 1, 1, 1)) return 0;
-    return upper_bytes(n, m_min, m_max, o, 64);
+    if (check_args(n, m_min, m_max, k, 1, 1)) return 0;
+    return upper_bytes(n, m_min, m_max, o, k);
 }
 
 int pmp_run_device(const double *d_series, int64_t n, int32_t m_min, int32_t m_max, int32_t k,

@@ -151,7 +151,7 @@ int pmp_submit(pmp_server *srv, const double *series, int64_t n, int32_t m_min, 
                uint64_t *req_id) {
     if (!srv || !series || !req_id) return PMP_EINVAL;
     if (k < 1 || exclusion < 1 || budget < 1) return PMP_EINVAL;
-    const size_t ws = pmp_workspace_bytes(n, m_min, m_max, opt);
+    const size_t ws = pmp_workspace_bytes(n, m_min, m_max, k, opt);
     if (ws == 0) return PMP_EINVAL;
     if (ws > srv->budget) return PMP_ENOMEM;
     for (int64_t i = 0; i < n; ++i)

@@ -92,7 +92,7 @@ def lib():
         L.pmp_default_options.argtypes = [vp]
         L.pmp_default_options.restype = None
         L.pmp_last_error.restype = C.c_char_p
-        L.pmp_workspace_bytes.argtypes = [i64, i32, i32, vp]
+        L.pmp_workspace_bytes.argtypes = [i64, i32, i32, i32, vp]
         L.pmp_workspace_bytes.restype = sz
         L.pmp_open.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp]
         L.pmp_open_ex.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, vp, vp]
@@ -150,8 +150,9 @@ def open_host(series, m_min: int, m_max: int, k: int, exclusion: int, budget: in
     return (res, st.as_dict()) if stats else res
 
 
-def workspace_bytes(n: int, m_min: int, m_max: int, opts: Options | None = None) -> int:
-    return int(lib().pmp_workspace_bytes(n, m_min, m_max,
+def workspace_bytes(n: int, m_min: int, m_max: int, k: int = 20,
+                    opts: Options | None = None) -> int:
+    return int(lib().pmp_workspace_bytes(n, m_min, m_max, k,
                                          C.byref(opts) if opts is not None else None))
 
 
@@ -181,7 +182,7 @@ def run_device(t_dev, m_min: int, m_max: int, k: int, exclusion: int, budget: in
     assert t_dev.dtype == torch.float64 and t_dev.is_cuda and t_dev.is_contiguous()
     n = t_dev.numel()
     ws = workspace or Workspace(t_dev.device)
-    need = workspace_bytes(n, m_min, m_max, opts)
+    need = workspace_bytes(n, m_min, m_max, k, opts)
     if need == 0:
         raise PMPError(PMP_EINVAL, "invalid arguments for the workspace query")
     wptr, wbytes = ws.get(need)

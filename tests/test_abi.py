@@ -40,13 +40,18 @@ def test_default_options_are_the_paper_constants():
 def test_workspace_query_and_argument_checks():
     from paper_2607_17481_amd import pmp
     assert pmp.workspace_bytes(100_000, 50, 100) > 0
-    assert pmp.workspace_bytes(100_000, 50, 100, pmp.options(precision=1)) < \
-        pmp.workspace_bytes(100_000, 50, 100, pmp.options(precision=0))
+    assert pmp.workspace_bytes(100_000, 50, 100, opts=pmp.options(precision=1)) < \
+        pmp.workspace_bytes(100_000, 50, 100, opts=pmp.options(precision=0))
     assert pmp.workspace_bytes(100, 2, 10) == 0          # m_min < 3
     assert pmp.workspace_bytes(100, 10, 101) == 0        # m_max > n
     assert pmp.workspace_bytes(100, 20, 10) == 0
     assert pmp.workspace_bytes(10_000, 100, 2048) > 0     # the longest supported window
     assert pmp.workspace_bytes(10_000, 100, 2049) == 0
+    assert pmp.workspace_bytes(10_000, 100, 200, k=0) == 0
+    # the selection buffers grow with k: 24 bytes per selected cell, k (m_max + 1) cells
+    w20 = pmp.workspace_bytes(10_000, 100, 2048, k=20)
+    w150 = pmp.workspace_bytes(10_000, 100, 2048, k=150)
+    assert w150 - w20 >= 24 * 130 * 2049
     with pytest.raises(pmp.PMPError) as e:
         pmp.open_host(np.zeros(10), 2, 5, 3, 1)
     assert e.value.code == pmp.PMP_EINVAL

@@ -426,6 +426,23 @@ def test_k_from_one_to_many(gpu, ws, oracle, prec, k):
     print(f"k={k} {prec}: certify rounds {st['certify_rounds']}")
 
 
+def test_queried_workspace_suffices_for_large_k_at_budget_one(gpu, oracle):
+    """A fresh workspace of the size pmp_workspace_bytes reports for this k
+    is enough at budget 1 and 8 signature bits (the deepest directories the
+    query assumes, and selection buffers of k (m_max + 1) cells), with
+    k = 150; against the full oracle profile."""
+    n, lo, hi, excl = 3000, 20, 40, 10
+    t = np.cumsum(np.random.default_rng(77).standard_normal(n))
+    if not _KSWEEP_ROWS:
+        _KSWEEP_ROWS.update(oracle.pan_profile(t, range(lo, hi + 1), excl))
+    fresh = gpu.Workspace("cuda:0")
+    res, st = run(gpu, fresh, t, lo, hi, excl, k=150, budget=1, signature_bits=8)
+    need = gpu.workspace_bytes(n, lo, hi, 150, gpu.options(signature_bits=8))
+    assert fresh.buf.numel() <= need + 256 and st["workspace_bytes"] <= need
+    ok, msg = parity.check_topk(res, _KSWEEP_ROWS, 150, oracle, t, excl=excl)
+    assert ok, msg
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_threshold_loop_past_first_round(gpu, ws, oracle, prec):
     """The certificate's threshold loop (Sec. 3.6; the greedy prefix up to T

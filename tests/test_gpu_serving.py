@@ -54,7 +54,7 @@ def test_alone_equals_in_the_mix(prec):
 def test_requests_overlap_and_admission():
     from paper_2607_17481_amd import pmp
     reqs = _requests(8, seed=9)
-    need = max(pmp.workspace_bytes(len(t), lo, hi) for t, lo, hi, _ in reqs)
+    need = max(pmp.workspace_bytes(len(t), lo, hi, 20) for t, lo, hi, _ in reqs)
     budget = 2 * need + (1 << 20)
     with pmp.Server(0, budget, slots=4) as srv:
         ids = [srv.submit(t, lo, hi, 20, ex) for t, lo, hi, ex in reqs]
@@ -70,7 +70,7 @@ def test_requests_overlap_and_admission():
 def test_refuses_what_can_never_fit_and_polls():
     from paper_2607_17481_amd import pmp
     t = synth.wafer_like(20_000, 5, copies=2)
-    need = pmp.workspace_bytes(len(t), 50, 60)
+    need = pmp.workspace_bytes(len(t), 50, 60, 20)
     with pmp.Server(0, need // 2, slots=2) as srv:
         with pytest.raises(pmp.PMPError) as e:
             srv.submit(t, 50, 60, 20, 50)
