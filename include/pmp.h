@@ -152,6 +152,26 @@ int pmp_run_device(const double *d_series, int64_t n, int32_t m_min,
                    void *stream, pmp_motif *out, int32_t *n_out,
                    pmp_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and result as pmp_run_device, with the workspace taken from a
+ * fixed device array of 256 MiB inside the library instead of a caller
+ * buffer.  Each GPU the library runs on holds that array until the process
+ * ends; its address is looked up on the first call on a device.  No device
+ * memory is allocated and no HIP event is created (pmp_stats then carries
+ * the counters but 0 for the phase times).
+ * The array is shared by every call on the same GPU and keeps the last
+ * call's contents (the pipeline initializes what it reads): calls that
+ * overlap on one GPU, from any thread or stream, race and must be
+ * serialized by the caller.
+ * Errors: as pmp_run_device; PMP_ENOMEM when the request's workspace bound
+ * (pmp_workspace_bytes) exceeds 256 MiB, about 500,000 cells in the FP64
+ * form. */
+int pmp_run_device_noalloc(const double *d_series, int64_t n, int32_t m_min,
+                           int32_t m_max, int32_t k, int32_t exclusion,
+                           int32_t budget, const pmp_options *opt, void *stream,
+                           pmp_motif *out, int32_t *n_out, pmp_stats *stats);
+
 /* ------------------------------------------------------------- serving */
 
 typedef struct pmp_server pmp_server;

@@ -1045,7 +1045,7 @@ static int run_pipeline(Run &R, Arena &ar) {
 static int run_device(const double *d_series, int64_t n, int32_t m_min, int32_t m_max, int32_t k,
                       int32_t excl, int32_t budget, const pmp_options *opt, void *ws,
                       size_t ws_bytes, void *stream, pmp_motif *out, int32_t *n_out,
-                      pmp_stats *stats, pmp_debug *dbg) {
+                      pmp_stats *stats, pmp_debug *dbg, bool timed = true) {
     g_err.clear();
     if (!d_series || !out || !n_out) return fail(PMP_EINVAL, "null argument");
     if (stats && stats->size != sizeof(pmp_stats)) return fail(PMP_EINVAL, "pmp_stats.size mismatch");
@@ -1070,6 +1070,7 @@ static int run_device(const double *d_series, int64_t n, int32_t m_min, int32_t 
     R.n_out = n_out;
     R.st = stats;
     R.dbg = dbg;
+    R.timed = timed;
     *n_out = 0;
     Arena ar;
     ar.base = (char *)ws;
@@ -1084,6 +1085,41 @@ static int run_device(const double *d_series, int64_t n, int32_t m_min, int32_t 
 }  // namespace pmp
 
 using namespace pmp;
+
+// ------------------------------------------ fixed device scratch
+// The workspace of pmp_run_device_noalloc: a device array of fixed size,
+// which every GPU the library runs on holds until the process ends.  In host
+// code its name is a host-side stand-in, never a device address: the address
+// on each device comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is handed to kernels.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+// Address of the scratch array on the current device (looked up on the first
+// call on that device).
+static int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PMP_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PMP_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PMP_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PMP_OK;
+}
 
 extern "C" {
 
@@ -1119,6 +1155,30 @@ int pmp_run_device(const double *d_series, int64_t n, int32_t m_min, int32_t m_m
                    pmp_stats *stats) {
     return run_device(d_series, n, m_min, m_max, k, exclusion, budget, opt, d_workspace, ws_bytes,
                       stream, out, n_out, stats, nullptr);
+}
+
+int pmp_run_device_noalloc(const double *d_series, int64_t n, int32_t m_min, int32_t m_max,
+                           int32_t k, int32_t exclusion, int32_t budget, const pmp_options *opt,
+                           void *stream, pmp_motif *out, int32_t *n_out, pmp_stats *stats) {
+    g_err.clear();
+    if (!d_series || !out || !n_out) return fail(PMP_EINVAL, "null argument");
+    int rc = check_args(n, m_min, m_max, k, exclusion, budget);
+    if (rc) return rc;
+    Opt o;
+    rc = read_options(opt, o);
+    if (rc) return rc;
+    const size_t need = upper_bytes(n, m_min, m_max, o, k);
+    if (need > kScratchBytes)
+        return fail(PMP_ENOMEM,
+                    "request needs up to %zu bytes of scratch; pmp_run_device_noalloc holds "
+                    "%zu (use pmp_run_device with a workspace)",
+                    need, kScratchBytes);
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    // no phase events: creating them would allocate
+    return run_device(d_series, n, m_min, m_max, k, exclusion, budget, opt, ws, kScratchBytes,
+                      stream, out, n_out, stats, nullptr, false);
 }
 
 int pmp_run_device_debug(const double *d_series, int64_t n, int32_t m_min, int32_t m_max,

@@ -99,6 +99,7 @@ def lib():
         L.pmp_run_device.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, sz, vp, vp, vp, vp]
         L.pmp_run_device_debug.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, sz, vp, vp,
                                            vp, vp, vp]
+        L.pmp_run_device_noalloc.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
         L.pmp_projection.argtypes = [u64, i32, i32, i32]
         L.pmp_projection.restype = C.c_double
         L.pmp_calibrate_width.argtypes = [vp, i64, i32, i32, i32, i32, i32, i32, vp]
@@ -198,6 +199,25 @@ def run_device(t_dev, m_min: int, m_max: int, k: int, exclusion: int, budget: in
         rc = lib().pmp_run_device_debug(*args, C.byref(debug))
     else:
         rc = lib().pmp_run_device(*args)
+    _check(rc)
+    return _motifs(out, n_out.value), st.as_dict()
+
+
+def run_device_noalloc(t_dev, m_min: int, m_max: int, k: int, exclusion: int, budget: int = 16,
+                       opts: Options | None = None, stream=None):
+    """pmp_run_device_noalloc on a torch float64 CUDA tensor (the library's
+    fixed scratch, no workspace); returns (motifs, stats dict)."""
+    import torch
+    assert t_dev.dtype == torch.float64 and t_dev.is_cuda and t_dev.is_contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(t_dev.device)
+    out = (MotifC * max(k, 1))()
+    n_out = C.c_int32(0)
+    st = Stats()
+    st.size = C.sizeof(Stats)
+    rc = lib().pmp_run_device_noalloc(C.c_void_p(t_dev.data_ptr()), t_dev.numel(), m_min, m_max,
+                                      k, exclusion, budget,
+                                      C.byref(opts) if opts is not None else None,
+                                      C.c_void_p(s.cuda_stream), out, C.byref(n_out), C.byref(st))
     _check(rc)
     return _motifs(out, n_out.value), st.as_dict()
 

@@ -1,0 +1,53 @@
+"""The no-allocation entry point (pmp_run_device_noalloc) against
+pmp_run_device, through the C ABI: the same motifs and counters on two calls
+in a row, the second with a smaller input, so the fixed scratch array is
+reused with the first call's contents still in it; and a clear refusal of a
+request whose workspace bound exceeds the array."""
+import numpy as np
+import pytest
+
+from paper_2607_17481_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+COUNTERS = ("K", "lengths", "certify_rounds", "cells", "indexed_cells", "threshold")
+
+
+def _both(pmp, torch, t, lo, hi, excl, prec):
+    td = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).cuda()
+    o = pmp.options(precision=prec)
+    print(f"[noalloc] n={len(t)} m={lo}..{hi} excl={excl} precision={prec}", flush=True)
+    got, st = pmp.run_device_noalloc(td, lo, hi, 20, excl, 16, o)
+    ref, st_ref = pmp.run_device(td, lo, hi, 20, excl, 16, o, pmp.Workspace("cuda:0"))
+    return got, st, ref, st_ref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_noalloc_equals_workspace_entry_point_twice(prec):
+    import torch
+    from paper_2607_17481_amd import pmp
+    big = synth.ecg_like(20_000, 41)
+    small = synth.wafer_like(8_000, 42, copies=4)
+    for t, lo, hi, excl in ((big, 40, 60, 40), (small, 30, 45, 30)):
+        got, st, ref, st_ref = _both(pmp, torch, t, lo, hi, excl, prec)
+        assert len(got) == 20
+        assert got == ref                       # cells, neighbours and distances, bit for bit
+        for c in COUNTERS:
+            assert st[c] == st_ref[c], c
+        assert st["ms_total"] == 0.0            # no phase events in this form
+        assert 0 < st["workspace_bytes"] <= 256 << 20
+
+
+def test_noalloc_refuses_what_does_not_fit():
+    import torch
+    from paper_2607_17481_amd import pmp
+    t = synth.wafer_like(100_000, 43, copies=4)
+    td = torch.from_numpy(t).cuda()
+    with pytest.raises(pmp.PMPError) as e:
+        pmp.run_device_noalloc(td, 50, 100, 20, 50)
+    assert e.value.code == pmp.PMP_ENOMEM
+    assert "pmp_run_device_noalloc holds" in str(e.value)
+    # and it still works afterwards
+    got, _ = pmp.run_device_noalloc(td[:6000].contiguous(), 50, 60, 20, 50)
+    ref, _ = pmp.run_device(td[:6000].contiguous(), 50, 60, 20, 50)
+    assert got == ref
