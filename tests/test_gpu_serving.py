@@ -26,8 +26,20 @@ def _requests(count, seed=3):
     return out
 
 
+_ORACLE_ROWS: dict = {}
+
+
+def _oracle_rows(oracle, x, t, lo, hi, ex):
+    """Exact rows of request x (oracle v2, equal to the brute force)."""
+    if x not in _ORACLE_ROWS:
+        _ORACLE_ROWS[x] = oracle.pan_profile_v2(t, range(lo, hi + 1), ex)
+    return _ORACLE_ROWS[x]
+
+
 @pytest.mark.parametrize("prec", [0, 1])
-def test_alone_equals_in_the_mix(prec):
+def test_alone_equals_in_the_mix(prec, oracle):
+    """Every served request equals its result alone (FP64 form: bit for bit)
+    and the oracle's exact top-k (every request here has n <= 1e5)."""
     import torch
     from paper_2607_17481_amd import pmp
     reqs = _requests(12)
@@ -42,13 +54,17 @@ def test_alone_equals_in_the_mix(prec):
     with pmp.Server(0, 24 << 30, slots=4) as srv:
         ids = [srv.submit(t, lo, hi, 20, ex, 16, opts) for t, lo, hi, ex in reqs]
         got = [srv.wait(i) for i in ids]
-    for (res, tm), ref in zip(got, alone):
+    for x, ((res, tm), ref, (t, lo, hi, ex)) in enumerate(zip(got, alone, reqs)):
         assert tm["end_s"] >= tm["start_s"] >= tm["submit_s"] > 0
         if prec == 0:
             assert res == ref
         else:
             ok, msg = parity.canonical_equal(res, [(r.i, r.j, r.m, r.dist) for r in ref])
             assert ok, msg
+        assert len(t) <= 100_000
+        ok, msg = parity.check_topk(res, _oracle_rows(oracle, x, t, lo, hi, ex), 20, oracle, t,
+                                    excl=ex)
+        assert ok, (x, msg)
 
 
 def test_requests_overlap_and_admission():
@@ -88,3 +104,18 @@ def test_refuses_what_can_never_fit_and_polls():
         with pytest.raises(pmp.PMPError) as e:
             srv.submit(bad, 50, 60, 20, 50)
         assert e.value.code == pmp.PMP_EINVAL
+
+
+def test_least_work_is_admitted_first():
+    """With one slot busy, queued requests start in order of estimated work
+    (cells x mean window length), not in arrival order."""
+    from paper_2607_17481_amd import pmp
+    busy = synth.ecg_like(300_000, 7)
+    sizes = {"large": 60_000, "small": 20_000, "tiny": 6_000}
+    series = {k: synth.wafer_like(v, 11, copies=2) for k, v in sizes.items()}
+    with pmp.Server(0, 16 << 30, slots=1) as srv:
+        first = srv.submit(busy, 100, 130, 20, 100)
+        ids = {k: srv.submit(series[k], 50, 70, 20, 50) for k in ("large", "small", "tiny")}
+        srv.wait(first)
+        starts = {k: srv.wait(i)[1]["start_s"] for k, i in ids.items()}
+    assert starts["tiny"] < starts["small"] < starts["large"], starts
