@@ -9,8 +9,11 @@ over one synthetic series already resident in HBM, with the workspace
 allocated beforehand; the results land in host memory.  The metric is
 samples x lengths per second, i.e. (sum over m of n - m + 1) per second.
 
-Prints one JSON line.  The CPU baseline times the CPU oracle on a bounded
-sample of the same workload (exact brute-force rows of randomly drawn cells).
+Prints one JSON line.  ms_per_step is the mean over the K timed steps (the
+value's denominator), ms_per_step_median the median step.  The CPU baseline
+times the CPU oracle on bounded samples of the same workload: oracle v2 on a
+prefix of the series, extrapolated to the full job, and oracle v1's exact rows
+of randomly drawn cells.
 """
 from __future__ import annotations
 
@@ -48,30 +51,77 @@ def make_series(name):
     return synth.random_walk_planted(n, seed=seed)[0]
 
 
-def cpu_baseline(t, name, target_s=12.0):
-    """The CPU oracle on a bounded sample: exact rows of random cells."""
+def cpu_model():
+    """The host CPU's model name, as lscpu reports it."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+V2_PREFIX = 200_000    # samples of the series the v2 baseline runs on
+
+
+def cpu_baseline(t, name, v1_seconds=6.0):
+    """The CPU oracle on bounded samples of the workload.
+
+    value: oracle v2 (the screened exact profile, equal to the brute force)
+    on the first V2_PREFIX samples of the same series at the first, middle
+    and last length, extrapolated to every length of the full series as
+    O(W^2) pairs (its cost per pair interpolated linearly in m between the
+    timed lengths); labelled an extrapolation when the prefix is shorter than
+    the series.  v1_rows: oracle v1's exact brute-force rows of cells drawn
+    uniformly from the full series, a direct sample."""
     from oracle import oracle as O
     O.build(force=False)
     _, n, _, m_min, m_max, step, excl, _ = WORKLOADS[name]
     lengths = list(range(m_min, m_max + 1, step))
-    rng = np.random.default_rng(7)
-    cells_done = 0
+    probe = sorted({lengths[0], lengths[len(lengths) // 2], lengths[-1]})
+    n_sub = min(n, V2_PREFIX)
+    sub = np.ascontiguousarray(t[:n_sub])
+
+    def pairs(w):
+        return max(w - excl, 0) * (max(w - excl, 0) + 1) / 2
+
+    per_pair = {}
     t0 = time.perf_counter()
-    rounds = 0
-    per = 16
-    while time.perf_counter() - t0 < target_s and rounds < 64:
+    for m in probe:
+        s0 = time.perf_counter()
+        O.profile_v2(sub, m, excl)
+        per_pair[m] = (time.perf_counter() - s0) / max(pairs(n_sub - m + 1), 1.0)
+    v2_s = time.perf_counter() - t0
+    est = 0.0
+    for m in lengths:
+        est += pairs(n - m + 1) * float(np.interp(m, probe, [per_pair[x] for x in probe]))
+    cells = synth.cells(n, lengths)
+    # v1: exact rows of random cells of the full series
+    rng = np.random.default_rng(7)
+    done, rounds, per = 0, 0, 16
+    s0 = time.perf_counter()
+    while time.perf_counter() - s0 < v1_seconds and rounds < 64:
         m = int(rng.choice(lengths))
-        starts = rng.integers(0, len(t) - m + 1, size=per)
-        O.cells(t, m, excl, starts)
-        cells_done += per
+        O.cells(t, m, excl, rng.integers(0, n - m + 1, size=per))
+        done += per
         rounds += 1
-    el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": cells_done / el, "unit": "samples*lengths/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{cells_done} cells ({rounds} lengths x {per} starts drawn uniformly) of "
-                      f"the same series, each an exact brute-force row incl. window statistics; "
-                      f"{el:.1f} s"}
+    v1_s = time.perf_counter() - s0
+    extrap = n_sub < n
+    return {"value": cells / est, "unit": "samples*lengths/s", "cores": O.threads(),
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": (f"oracle v2 on the first {n_sub} samples at m = {probe} "
+                       f"({v2_s:.1f} s), " +
+                       (f"extrapolated as O(W^2) pairs to n = {n} and all {len(lengths)} lengths "
+                        f"(estimated full job {est / 3600:.1f} h)" if extrap else
+                        f"all {len(lengths)} lengths estimated from these ({est:.1f} s)")),
+            "extrapolated": extrap,
+            "v1_rows": {"value": done / v1_s, "unit": "samples*lengths/s",
+                        "sample": f"{done} cells ({rounds} lengths x {per} starts drawn "
+                                  f"uniformly) of the full series, each an exact brute-force "
+                                  f"row incl. window statistics; {v1_s:.1f} s"}}
 
 
 TILE_W = 1024          # windows per sketch tile
@@ -86,9 +136,11 @@ def algorithmic_bytes(n, lengths, st, fs):
         w = n - m + 1
         rd += 12 * (w + -(-w // TILE_W) * (m - 1))   # samples + change-point prefix
     nx = st["indexed_cells"]
-    # per indexed window: cell, mu, 1/sigma, P, record, key word, sort key and
-    # value, join record
-    sketch = rd + nx * (4 + 8 + 8 + 8 + REC * fs + 8 + 4 + 4 + 32)
+    # the sketch phase, per indexed window: the sketch kernel writes cell,
+    # mu, 1/sigma, P and the record; the keys kernel reads the record back and
+    # writes the join operands (128), their metadata (16), the principal
+    # coordinates (16), the key word (8) and the sort key and value (4 + 4)
+    sketch = rd + nx * (4 + 8 + 8 + 8 + REC * fs) + nx * (REC * fs + 128 + 16 + 16 + 8 + 4 + 4)
     # per query: its state; per inspected candidate: slot, P, record; per
     # verified pair: the candidate's moments and the two cell updates (the
     # samples of both windows are read from the series, which stays resident
@@ -353,9 +405,12 @@ def main():
         pmp.run_device(td, m_min, m_max, k, excl, 16, opts, ws, stream)
     torch.cuda.synchronize()
     stats = []
+    step_ms = []          # each call returns with its results in host memory
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        s0 = time.perf_counter()
         res, st = pmp.run_device(td, m_min, m_max, k, excl, 16, opts, ws, stream)
+        step_ms.append((time.perf_counter() - s0) * 1e3)
         stats.append(st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -382,6 +437,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": float(np.median(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -418,11 +474,18 @@ def main():
             pmp.run_device(td, m_min, m_max, k, excl, 16, o2, ws, stream)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
+            ms2 = []
             for _ in range(args.steps):
+                s1 = time.perf_counter()
                 r2, s2 = pmp.run_device(td, m_min, m_max, k, excl, 16, o2, ws, stream)
+                ms2.append((time.perf_counter() - s1) * 1e3)
             torch.cuda.synchronize()
             el2 = time.perf_counter() - t1
-            forms[name] = {"ms_per_step": el2 * 1e3 / args.steps, "value": cells * args.steps / el2,
+            forms[name] = {"ms_per_step": el2 * 1e3 / args.steps,
+                           "ms_per_step_median": float(np.median(ms2)),
+                           "value": cells * args.steps / el2,
+                           "phase_ms": {p: s2["ms_" + p] for p in
+                                        ("sketch", "sort", "probe", "join", "rows")},
                            "same_top_k": [(x.i, x.m) for x in r2] == [(x.i, x.m) for x in res],
                            "max_rel_dist_err": max([abs(a.dist - b.dist) / max(b.dist, 1e-300)
                                                     for a, b in zip(r2, res)] + [0.0])}

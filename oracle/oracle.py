@@ -59,6 +59,7 @@ def lib():
         L.orc_profile.argtypes = [P, i64, i32, i32, P, P]
         L.orc_cells.argtypes = [P, i64, i32, i32, P, i64, i32, P, P]
         L.orc_profile_v2.argtypes = [P, i64, i32, i32, d, P, P, P, P]
+        L.orc_threads.restype = C.c_int
         L.orc_kprime.argtypes = [i32, i32]
         L.orc_kprime.restype = i32
         L.orc_features.argtypes = [P, i64, i32, i64, i32, P]
@@ -137,6 +138,11 @@ def pan_profile_v2(t, lengths, excl: int, progress=None):
         if progress:
             progress(int(m), nd)
     return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def cells(t, m: int, excl: int, starts, stop_at_zero: bool = False):

@@ -42,6 +42,16 @@
 
 #define ORC_EPS0 1e-6
 
+/* OpenMP threads of the parallel loops below (1 without OpenMP). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------------------- moments */
 
 /* Two-pass population moments of one window (Sec. 3.2 running moments). */
