@@ -295,15 +295,25 @@ def serving_sweep(cfg, capacity=None):
 
 
 PARAM_SWEEP = {"alpha": (4, 8, 16, 32, 64), "K": (4, 8, 12, 16), "maxperf": (4, 4)}
+# the paper's App. E study of the anchor stride, the sieve width, the local
+# completion's round cap and radii; each entry: label, options
+EMIT_SWEEP = (
+    [(f"stride {s}", dict(anchor_stride=s)) for s in (1, 2, 3, 4, 6, 8)]
+    + [(f"sieve w {w}", dict(sieve_width=w)) for w in (0, 2, 8, 32)]
+    + [(f"rounds {r}", dict(complete_rounds=r)) for r in (0, 1, 8)]
+    + [(f"radii {dm},{dp}", dict(complete_dm=dm, complete_dp=dp)) for dm, dp in ((2, 1), (12, 8))]
+)
 
 
-def param_sweep(workload, precision, steps=2):
+def param_sweep(workload, precision, steps=2, emit=False):
     """Runtime against the occupancy target alpha (spectral width calibrated)
     and against the spectral width K (alpha = 16), and at alpha = 4, K = 4
-    (the paper's maximum-performance constants that apply here; its anchor
-    stride and P_max have no counterpart).  The exact top-k is the same in
-    every configuration (Prop. 2); each run is checked against the default
-    one."""
+    (the paper's maximum-performance constants that apply here; its P_max
+    has no counterpart here); with `emit`, against the anchor stride, the
+    sieve width, the completion round cap and radii instead (each varied
+    alone from the defaults).  The exact top-k is the same in every
+    configuration (Prop. 2 for K; the certificate for the rest); each run is
+    checked against the default one."""
     import torch
     from paper_2607_17481_amd import pmp
     gen, n, seed, m_min, m_max, step, excl, k = WORKLOADS[workload]
@@ -314,38 +324,53 @@ def param_sweep(workload, precision, steps=2):
     ws = pmp.Workspace(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def run(alpha, K):
-        o = pmp.options(m_step=step, precision=PREC[precision], spectral_width=K)
+    def run(alpha, K, label="", **kw):
+        o = pmp.options(m_step=step, precision=PREC[precision], spectral_width=K, **kw)
         pmp.run_device(td, m_min, m_max, k, excl, alpha, o, ws, stream)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ms = []
         for _ in range(steps):
+            t0 = time.perf_counter()
             res, st = pmp.run_device(td, m_min, m_max, k, excl, alpha, o, ws, stream)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        r = {"alpha": alpha, "K": st["K"], "ms_per_step": ms, "value": cells * 1e3 / ms,
-             "phase_ms": {p: st["ms_" + p] for p in ("sketch", "sort", "probe", "join", "rows")},
+            ms.append((time.perf_counter() - t0) * 1e3)
+        r = {"label": label, "alpha": alpha, "K": st["K"], "options": kw,
+             "ms_per_step": float(np.median(ms)), "value": cells * 1e3 / float(np.median(ms)),
+             "phase_ms": {p: st["ms_" + p] for p in ("sketch", "sort", "probe", "complete",
+                                                     "join", "rows")},
+             "emit_ms": {p: st["ms_" + p] for p in ("sieve", "hints")},
              "pass_candidates": st["pass_candidates"], "pass_verified": st["pass_verified"],
+             "sieve_verified": st["sieve_verified"], "hint_verified": st["hint_verified"],
+             "complete_verified": st["complete_verified"], "complete_rounds": st["complete_rounds"],
              "join_candidates": st["join_candidates"], "join_verified": st["join_verified"],
-             "certify_rounds": st["certify_rounds"]}
-        print(f"  alpha {alpha} K {st['K']}: {ms:.1f} ms", file=sys.stderr, flush=True)
+             "join_pairs": st["join_pairs"], "certify_rounds": st["certify_rounds"]}
+        tag = label or f"alpha {alpha} K {st['K']}"
+        print(f"  {tag}: {r['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
         return r, [(x.i, x.j, x.m, x.dist) for x in res]
 
-    base, ref = run(16, 0)
-    out = {"metric": "runtime against alpha and K", "workload": workload, "precision": precision,
-           "cells": cells, "steps": steps, "default": base, "alpha": [], "K": [], "maxperf": None}
+    base, ref = run(16, 0, "default")
+    out = {"metric": "runtime against " + ("the emit-stage constants" if emit else "alpha and K"),
+           "workload": workload, "precision": precision, "cells": cells, "steps": steps,
+           "default": base}
     same = True
-    for a in PARAM_SWEEP["alpha"]:
-        r, top = run(a, 0)
+    if emit:
+        out["runs"] = []
+        for label, kw in EMIT_SWEEP:
+            r, top = run(16, 0, label, **kw)
+            same &= top == ref
+            out["runs"].append(r)
+    else:
+        out.update({"alpha": [], "K": [], "maxperf": None})
+        for a in PARAM_SWEEP["alpha"]:
+            r, top = run(a, 0)
+            same &= top == ref
+            out["alpha"].append(r)
+        for K in PARAM_SWEEP["K"]:
+            r, top = run(16, K)
+            same &= top == ref
+            out["K"].append(r)
+        r, top = run(*PARAM_SWEEP["maxperf"])
         same &= top == ref
-        out["alpha"].append(r)
-    for K in PARAM_SWEEP["K"]:
-        r, top = run(16, K)
-        same &= top == ref
-        out["K"].append(r)
-    r, top = run(*PARAM_SWEEP["maxperf"])
-    same &= top == ref
-    out["maxperf"] = r
+        out["maxperf"] = r
     out["same_top_k"] = same
     print(json.dumps(out), flush=True)
 
@@ -372,6 +397,8 @@ def main():
                     help="capacity (requests/s) to take instead of measuring it")
     ap.add_argument("--param-sweep", action="store_true",
                     help="only run the alpha / K sweep on --workload")
+    ap.add_argument("--emit-sweep", action="store_true",
+                    help="only run the anchor stride / sieve / completion sweep on --workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the workload fits one MI355X); "
@@ -385,8 +412,8 @@ def main():
                    loads=tuple(float(x) for x in args.sweep_loads.split(",")))
         serving_sweep(cfg, args.sweep_capacity)
         return
-    if args.param_sweep:
-        param_sweep(args.workload, args.precision)
+    if args.param_sweep or args.emit_sweep:
+        param_sweep(args.workload, args.precision, emit=args.emit_sweep)
         return
 
     import torch
@@ -448,7 +475,11 @@ def main():
                    "cells": cells, "precision": args.precision, "budget_alpha": 16},
         "onepass_ms": avg("ms_onepass"),
         "exact_ms": avg("ms_total"),
-        "phase_ms": {p: avg("ms_" + p) for p in ("sketch", "sort", "probe", "join", "rows")},
+        "phase_ms": {p: avg("ms_" + p) for p in ("sketch", "sort", "probe", "complete", "join",
+                                                 "rows")},
+        "emit_ms": {p: avg("ms_" + p) for p in ("sieve", "hints")},
+        "emit": {c: last[c] for c in ("anchors", "sieve_verified", "hint_verified",
+                                      "complete_verified", "complete_rounds", "hot_buckets")},
         "certify_rounds": last["certify_rounds"],
         "K": last["K"],
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
@@ -485,7 +516,7 @@ def main():
                            "ms_per_step_median": float(np.median(ms2)),
                            "value": cells * args.steps / el2,
                            "phase_ms": {p: s2["ms_" + p] for p in
-                                        ("sketch", "sort", "probe", "join", "rows")},
+                                        ("sketch", "sort", "probe", "complete", "join", "rows")},
                            "same_top_k": [(x.i, x.m) for x in r2] == [(x.i, x.m) for x in res],
                            "max_rel_dist_err": max([abs(a.dist - b.dist) / max(b.dist, 1e-300)
                                                     for a, b in zip(r2, res)] + [0.0])}

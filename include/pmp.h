@@ -78,6 +78,25 @@ typedef struct {
     int32_t  gamma;           /* R = gamma * budget, default 8 (Sec. 3.4)     */
     int32_t  probe_ref_depth; /* d0, default 12 (Sec. 3.4)                    */
     int32_t  probe_cap;       /* cap on Hamming-1 probes, default 8           */
+    /* Anchor lengths and emit-time completion (Sec. 3.3, Sec. 3.6,
+     * Algorithm 2).  They change only how fast the certificate's threshold
+     * is reached, never the result. */
+    int32_t  anchor_stride;   /* s: the one pass probes every s-th length of
+                                 the list and the last; the lengths between
+                                 are re-cut from their neighbours' partners;
+                                 default 6 (the paper's maximum-performance
+                                 stride), 1 = every length                    */
+    int32_t  sieve_width;     /* w of the hot-class sieve over buckets of more
+                                 than R entries, default 0 = off (the paper
+                                 uses 8; here it costs time and lowers none
+                                 of the cells the certificate needs)          */
+    int32_t  complete_rounds; /* P_max rounds of local completion around the
+                                 top-k cells, default 8; 0 = off (also off
+                                 when anchor_stride is 1)                     */
+    int32_t  complete_dm;     /* Delta_m of the completion box, in window
+                                 length, default 6                            */
+    int32_t  complete_dp;     /* Delta_p of the completion box, in samples,
+                                 default 4                                    */
     int32_t  reserved;
 } pmp_options;
 
@@ -102,7 +121,8 @@ typedef struct {
     double   threshold;         /* final certified threshold T                */
     double   ms_total;          /* device time of the whole call              */
     double   ms_onepass;        /* moments + sketch + buckets + probe         */
-    double   ms_certify;        /* selection + threshold join + exact rows    */
+    double   ms_certify;        /* selection + threshold join + exact rows
+                                   (after the emit stage, ms_complete)        */
     double   ms_sketch;
     double   ms_sort;
     double   ms_probe;
@@ -110,6 +130,14 @@ typedef struct {
     double   ms_rows;
     uint64_t workspace_bytes;   /* device bytes used by the call              */
     uint64_t join_pairs;        /* pairs the join's MFMA filter evaluated     */
+    uint64_t sieve_verified;    /* exact distances of the hot-class sieve     */
+    uint64_t hint_verified;     /* exact distances re-cut from anchor hints   */
+    uint64_t complete_verified; /* exact distances of local completion        */
+    double   ms_complete;       /* sieve + hints + local completion           */
+    int32_t  complete_rounds;   /* rounds of local completion run             */
+    int32_t  anchors;           /* anchor lengths probed                      */
+    double   ms_sieve;          /* the hot-class sieve (part of ms_complete)  */
+    double   ms_hints;          /* the hints (part of ms_complete)            */
 } pmp_stats;
 
 /* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),

@@ -21,7 +21,8 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpmp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_scan.hip", "k_sketch.hip", "k_probe.hip", "k_certify.hip", "k_join.hip",
+SOURCES = ["k_scan.hip", "k_sketch.hip", "k_probe.hip", "k_complete.hip", "k_certify.hip",
+           "k_join.hip",
            "pmp_host.hip",
            "pmp_server.cpp"]
 

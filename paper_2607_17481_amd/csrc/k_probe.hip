@@ -47,21 +47,35 @@ struct QwinA {
 };
 
 // Queries are taken in (length, start) order (indexed position k), so that
-// neighbouring windows, which tend to cost alike, share a wavefront.  A block
-// is one wavefront: wavefront times vary over two orders of magnitude, and a
-// single-wave block lets a compute unit start new work as soon as any one
-// wavefront ends, not when a slot for four is free.
+// neighbouring windows, which tend to cost alike, share a wavefront; only the
+// anchor lengths are probed (Sec. 3.3), each from its first probe block, so a
+// wavefront never spans two lengths.  A block is one wavefront: wavefront
+// times vary over two orders of magnitude, and a single-wave block lets a
+// compute unit start new work as soon as any one wavefront ends, not when a
+// slot for four is free.  Whenever a verification lowers a cell, the partner's
+// start is recorded as the cell's hint (any partner that lowered it will do:
+// the hints only propose pairs at the lengths between anchors).
 // Four wavefronts per SIMD (128 registers, a few spilled) hide more of the
 // candidate chain's latency than three without spills.
 template <typename FT>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4)))
-void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
-    const int64_t k_first = (int64_t)blockIdx.x * kWave;
+void k_probe(Req q, const uint32_t *__restrict__ bstart, int qcap) {
+    // the anchor length of this block: the last length whose first probe
+    // block is at or below it (uniform)
+    int lb = 0;
+    {
+        int hi = q.L - 1;
+        while (lb < hi) {
+            const int mid = (lb + hi + 1) >> 1;
+            if (q.len[mid].pblk_base <= (int64_t)blockIdx.x) lb = mid; else hi = mid - 1;
+        }
+    }
+    const int64_t k_first = q.len[lb].kbase + ((int64_t)blockIdx.x - q.len[lb].pblk_base) * kWave;
     const int64_t k = k_first + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
 
     // ---- per-lane query state
-    bool done = k >= N;
+    bool done = k >= q.len[lb].kbase + q.len[lb].n_index;
     int l = -1, m = 0, d = 0, probes = 0;
     int64_t cell_base = 0;
     uint32_t cq = 0, prefix = 0, lim = 0;
@@ -72,7 +86,7 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
     const uint32_t *bb = bstart;
     const FT *fq = (const FT *)q.F;
     if (!done) {
-        l = find_len_k_wave(q.len, q.L, k_first, k);
+        l = lb;
         const LenInfo L = q.len[l];
         m = L.m;
         d = L.depth;
@@ -203,8 +217,12 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
             if (dd < Pq) {
                 atomicMin((unsigned long long *)&q.P[k], db);
                 Pq = dd;
+                q.hint[k] = (uint32_t)pic;
             }
-            if (dd < pPc) atomicMin((unsigned long long *)&q.P[pc], db);
+            if (dd < pPc) {
+                atomicMin((unsigned long long *)&q.P[pc], db);
+                q.hint[pc] = (uint32_t)iq;
+            }
             has = false;
             if (Pq == 0.0) done = true;
         };
@@ -223,8 +241,12 @@ void k_probe(Req q, const uint32_t *__restrict__ bstart, int64_t N, int qcap) {
             if (dd < Pq) {
                 atomicMin((unsigned long long *)&q.P[k], db);
                 Pq = dd;
+                q.hint[k] = (uint32_t)s_ic[1][ln];
             }
-            if (dd < pPc1) atomicMin((unsigned long long *)&q.P[pc1], db);
+            if (dd < pPc1) {
+                atomicMin((unsigned long long *)&q.P[pc1], db);
+                q.hint[pc1] = (uint32_t)iq;
+            }
             if (Pq == 0.0) done = true;
         };
         if (mask1) {
@@ -264,16 +286,16 @@ __global__ __launch_bounds__(kBlock) void k_hot_buckets(const uint32_t *__restri
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, int max_m,
-                  hipStream_t s) {
-    if (N <= 0) return;
-    const dim3 grid((unsigned)((N + kWave - 1) / kWave));
+void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t nblocks,
+                  int max_m, hipStream_t s) {
+    if (nblocks <= 0) return;
+    const dim3 grid((unsigned)nblocks);
     const int qcap = kQwinExtra + max_m;
     const size_t lds = (size_t)qcap * sizeof(double);
     if (precision == 0)
-        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), lds, s, q, bstart, N, qcap);
+        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), lds, s, q, bstart, qcap);
     else
-        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), lds, s, q, bstart, N, qcap);
+        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), lds, s, q, bstart, qcap);
 }
 
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,

@@ -214,6 +214,10 @@ __device__ __forceinline__ void tile_positions_and_moments(
         }
     }
     __syncthreads();
+    // the cell -> indexed position map (anchors and hints need it)
+    if (q.kmap)
+        for (int w = tid; w < nw; w += kBlock)
+            q.kmap[L.cell_base + i0 + w] = kpos[w] < 0 ? kNone : (uint32_t)kpos[w];
     int nix = 0;                                        // non-constant windows of the tile
     for (int v = 0; v < kBlock / kWave; ++v) nix += (int)wsum[v];
 

@@ -40,6 +40,16 @@ struct LenInfo {
     int64_t n_index;      // non-constant windows (entries of the directory)
     int64_t tile_base;    // first sketch tile of this length
     int64_t blk_base;     // first block of this length in k_keys
+    // anchor lengths (Sec. 3.3): the one pass probes only these.  pblk_base
+    // is non-decreasing over the lengths: an anchor owns probe blocks
+    // [pblk_base, pblk_base + ceil(n_index / 64)), a non-anchor none.
+    // Likewise hblk_base for the hint blocks of the non-anchor lengths.
+    int32_t anchor;       // 1: an anchor length
+    int32_t a_lo, a_hi;   // a non-anchor's nearest anchors below and above
+                          // (indices; -1: none)
+    int32_t pad_;
+    int64_t pblk_base;    // first probe block of this length
+    int64_t hblk_base;    // first hint block of this length
 };
 
 // Everything a kernel needs to know about one request.
@@ -73,14 +83,21 @@ struct Req {
     uint32_t *perm;        // [N] slot -> k
     uint32_t *pcell;       // [N] slot -> cell
     const float *gproj;    // [L][B][30] SimHash projections
+    uint32_t *kmap;        // [cells] cell -> indexed position k (kNone: constant);
+                           // written by the sketch when not null
+    uint32_t *hint;        // [N] start of a partner that lowered the cell
+                           // (kNone: none), written when a cell is lowered
     float   *emax;         // [L] largest e_i of each length
     unsigned long long *counters;   // stats counters
     int     *bad;          // raised on inputs the library cannot represent
 };
 
 enum Counter {
-    C_PASS_CAND = 0, C_PASS_VER, C_JOIN_CAND, C_JOIN_VER, C_HOT, C_JOIN_PAIRS, C_NCOUNTERS
+    C_PASS_CAND = 0, C_PASS_VER, C_JOIN_CAND, C_JOIN_VER, C_HOT, C_JOIN_PAIRS,
+    C_SIEVE_VER, C_HINT_VER, C_COMPL_VER, C_COMPL_IMPROVED, C_NCOUNTERS
 };
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;      // no entry (kmap, hint)
 
 // ------------------------------------------------------------- helpers
 
@@ -429,10 +446,27 @@ void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const ui
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 // (k_probe.hip)
-void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t N, int max_m,
-                  hipStream_t s);
+// one wavefront per 64 indexed windows of each anchor length (LenInfo.pblk_base)
+void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t nblocks,
+                  int max_m, hipStream_t s);
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,
                         hipStream_t s);
+// (k_complete.hip): the emit stage
+// the hints: one wavefront per 64 indexed windows of each length between
+// anchors (LenInfo.hblk_base)
+void launch_hints(int precision, const Req &q, int64_t nblocks, hipStream_t s);
+void launch_sieve_count(const Req &q, const uint32_t *bstart, int64_t nbuckets, int R,
+                        uint32_t *cnt, hipStream_t s);
+void launch_sieve_keys(int precision, const Req &q, const uint32_t *bstart, const uint32_t *off,
+                       int64_t nbuckets, uint32_t total, const float *dir, uint32_t *key,
+                       uint32_t *val, uint32_t *seg, hipStream_t s);
+void launch_sieve_regroup(const uint32_t *val, const uint32_t *seg, uint32_t total, uint32_t *key2,
+                          hipStream_t s);
+void launch_sieve_verify(int precision, const Req &q, const uint32_t *bstart, const uint32_t *off,
+                         const uint32_t *order, const uint32_t *seg, uint32_t total, int w,
+                         hipStream_t s);
+void launch_complete(int precision, const Req &q, const uint32_t *seeds, int nseeds, int dm,
+                     int dp, hipStream_t s);
 // (k_certify.hip)
 int64_t select_blocks(int64_t n);
 // The first `need` values of P in (value, position) order: positions below the

@@ -57,6 +57,15 @@ struct Opt {
     int gamma = 8;
     int d0 = 12;
     int probe_cap = 8;
+    // anchor lengths and emit-time completion (Sec. 3.3, 3.6).  The stride is
+    // the paper's maximum-performance one (App. E; its default is 2) and the
+    // sieve is off (its default width is 8): both measured faster here, and
+    // neither changes the certified result
+    int stride = 6;
+    int sieve_w = 0;
+    int compl_rounds = 8;
+    int compl_dm = 6;
+    int compl_dp = 4;
 };
 
 static int read_options(const pmp_options *o, Opt &out) {
@@ -74,6 +83,11 @@ static int read_options(const pmp_options *o, Opt &out) {
         d.gamma = o->gamma;
         d.d0 = o->probe_ref_depth;
         d.probe_cap = o->probe_cap;
+        d.stride = o->anchor_stride;
+        d.sieve_w = o->sieve_width;
+        d.compl_rounds = o->complete_rounds;
+        d.compl_dm = o->complete_dm;
+        d.compl_dp = o->complete_dp;
     }
     if (d.m_step < 1) return fail(PMP_EINVAL, "m_step must be >= 1");
     if (d.precision < 0 || d.precision > 2) return fail(PMP_EINVAL, "unknown precision");
@@ -83,6 +97,11 @@ static int read_options(const pmp_options *o, Opt &out) {
     if (d.d0 < 0) return fail(PMP_EINVAL, "probe_ref_depth must be >= 0");
     if (d.probe_cap < 0 || d.probe_cap > kProbeSlots) return fail(PMP_EINVAL, "probe_cap in [0,8]");
     if (d.certify != 0 && d.certify != 1) return fail(PMP_EINVAL, "certify is 0 or 1");
+    if (d.stride < 1) return fail(PMP_EINVAL, "anchor_stride must be >= 1");
+    if (d.sieve_w < 0 || d.sieve_w > 64) return fail(PMP_EINVAL, "sieve_width in [0,64]");
+    if (d.compl_rounds < 0 || d.compl_rounds > 64) return fail(PMP_EINVAL, "complete_rounds in [0,64]");
+    if (d.compl_dm < 0 || d.compl_dp < 0 || d.compl_dp > 64)
+        return fail(PMP_EINVAL, "complete_dm >= 0 and complete_dp in [0,64]");
     out = d;
     return PMP_OK;
 }
@@ -315,6 +334,8 @@ struct Plan {
     std::vector<int> ms;
     std::vector<LenInfo> len;
     int64_t cells = 0, ntiles = 0, nbuckets = 0, N = 0, nkblocks = 0;
+    int64_t nprobe_blocks = 0, nhint_blocks = 0;
+    int anchors = 0;
     int max_m = 0, len_bits = 0, key_shift = 0, jkey_shift = 0, max_depth = 0;
 };
 
@@ -347,6 +368,24 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
     int64_t kb = 0, bb = 0;
     p.max_depth = 0;
     p.nkblocks = 0;
+    // anchor lengths (Sec. 3.3): every stride-th length of the list, and the
+    // last one; each other length knows its nearest anchors
+    p.anchors = 0;
+    for (int l = 0; l < p.L; ++l) {
+        LenInfo &L = p.len[l];
+        L.anchor = (l % o.stride == 0 || l == p.L - 1) ? 1 : 0;
+        p.anchors += L.anchor;
+        L.a_lo = L.a_hi = -1;
+        L.pad_ = 0;
+    }
+    for (int l = 0; l < p.L; ++l) {
+        if (p.len[l].anchor) continue;
+        for (int a = l - 1; a >= 0 && p.len[l].a_lo < 0; --a)
+            if (p.len[a].anchor) p.len[l].a_lo = a;
+        for (int a = l + 1; a < p.L && p.len[l].a_hi < 0; ++a)
+            if (p.len[a].anchor) p.len[l].a_hi = a;
+    }
+    p.nprobe_blocks = p.nhint_blocks = 0;
     for (int l = 0; l < p.L; ++l) {
         LenInfo &L = p.len[l];
         L.kprime = kprime_of(K, L.m);
@@ -360,6 +399,12 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
         L.kbase = kb;
         L.blk_base = p.nkblocks;
         p.nkblocks += (L.n_index + kBlock - 1) / kBlock;
+        L.pblk_base = p.nprobe_blocks;
+        L.hblk_base = p.nhint_blocks;
+        if (L.anchor)
+            p.nprobe_blocks += (L.n_index + kWave - 1) / kWave;
+        else
+            p.nhint_blocks += (L.n_index + kWave - 1) / kWave;
         L.bucket_base = bb;
         kb += L.n_index;
         bb += (int64_t)1 << d;
@@ -399,6 +444,10 @@ struct Bufs {
     uint32_t *skey, *sval, *skey2, *sval2, *pcell, *bstart;
     void *sort_tmp;
     uint32_t *jk, *jv, *jk2, *jv2;
+    // emit stage: cell -> k map, partner hints, sieve segments and
+    // directions, completion seeds
+    uint32_t *kmap, *hint, *scnt, *stotal, *sseg, *seeds;
+    float *sdir;
     uint32_t *sel_cnt;
     // the selection's results, one contiguous block read back at once:
     // state, then less_val, less_k, less_cell, eq_k, eq_cell (need each)
@@ -417,8 +466,10 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.flags = take<uint32_t>(a, p.n + 1);
     b.E = take<uint32_t>(a, p.n + 1);
     b.tile_off = take<uint32_t>(a, p.ntiles + 1);
+    // the scans run over n + 1 change points, the tiles, the selection's
+    // blocks and the sieve's buckets (at most 2 W + 1 per length)
     b.scan_tmp = (uint32_t *)a.take(scan_temp_bytes(std::max<int64_t>(
-        {p.n + 1, p.ntiles + 1, select_blocks(p.cells) + 1, p.cells})));
+        {p.n + 1, p.ntiles + 1, select_blocks(p.cells) + 1, 2 * p.cells + p.L + 1})));
     b.bad = take<int>(a, 1);
     b.counters = take<unsigned long long>(a, C_NCOUNTERS);
     b.emax = take<float>(a, p.L);
@@ -440,9 +491,15 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.row_arg = take<unsigned long long>(a, k);
     b.cal_starts = take<int64_t>(a, 3 * 256);
     b.cal_win = take<double>(a, (int64_t)3 * 256 * p.max_m);
+    b.sdir = take<float>(a, (int64_t)p.L * kFD);
+    b.seeds = take<uint32_t>(a, k);
+    b.stotal = take<uint32_t>(a, 1);
 }
 
-static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
+static bool needs_kmap(const Opt &o) { return o.stride > 1; }
+
+static void carve2(Arena &a, Bufs &b, const Plan &p, const Opt &o, int k) {
+    const int precision = o.precision;
     const int64_t N = std::max<int64_t>(p.N, 1);
     const int64_t need = need_select(k, p.max_m);
     b.cell = take<uint32_t>(a, N);
@@ -474,6 +531,10 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, int precision, int k) {
     b.less_cell = b.less_k + need;
     b.eq_k = b.less_cell + need;
     b.eq_cell = b.eq_k + need;
+    b.kmap = needs_kmap(o) ? take<uint32_t>(a, p.cells) : nullptr;
+    b.hint = take<uint32_t>(a, N);
+    b.scnt = o.sieve_w > 0 ? take<uint32_t>(a, p.nbuckets + 1) : nullptr;
+    b.sseg = o.sieve_w > 0 ? take<uint32_t>(a, N) : nullptr;
 }
 
 // ------------------------------------------------------------ selection
@@ -560,12 +621,10 @@ static int select_topk(const Plan &p, Bufs &b, int k, hipStream_t s, std::vector
     return PMP_OK;
 }
 
-// ------------------------------------------------------------- pipeline
-
 // Phase times from HIP events on the request's stream.  Off (no events
 // created at all) for callers that must not allocate.
 struct Timer {
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[11] = {};
     bool ok = false;
     explicit Timer(bool on) {
         if (!on) return;
@@ -586,6 +645,94 @@ struct Timer {
         return 0.0;
     }
 };
+
+// ------------------------------------------------------------ emit stage
+
+// The hot-class sieve (Sec. 3.6): members of the anchor lengths' buckets of
+// more than R entries, sorted by one seeded Gaussian projection within their
+// bucket, each verified against the w members after it.
+static int run_sieve(const Plan &p, Bufs &b, const Req &q, const Opt &o, hipStream_t s) {
+    launch_sieve_count(q, b.bstart, p.nbuckets, q.budget_R, b.scnt, s);
+    scan_exclusive_u32(b.scnt, b.scnt, p.nbuckets, b.stotal, b.scan_tmp, s);
+    uint32_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, b.stotal, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (total == 0) return PMP_OK;
+    if ((int64_t)total > p.N) return fail(PMP_EINTERNAL, "sieve member count %u > %lld", total,
+                                          (long long)p.N);
+    launch_sieve_keys(o.precision, q, b.bstart, b.scnt, p.nbuckets, total, b.sdir, b.jk, b.jv,
+                      b.sseg, s);
+    radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, total, 0, 32, b.sort_tmp, s);
+    launch_sieve_regroup(b.jv, b.sseg, total, b.jk, s);
+    int bits = 1;
+    while (((int64_t)1 << bits) < p.nbuckets) ++bits;
+    radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, total, 0, bits, b.sort_tmp, s);
+    launch_sieve_verify(o.precision, q, b.bstart, b.scnt, b.jv, b.sseg, total, o.sieve_w, s);
+    return PMP_OK;
+}
+
+// Sieve, hints at the lengths between anchors, then local completion around
+// the current top-k for up to P_max rounds, each round's seeds re-selected,
+// until a round lowers no cell.  `selected`: `acc` holds the selection of the
+// final upper profile (otherwise the caller selects); `rounds`: completion
+// rounds run.
+static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipStream_t s,
+                      Timer &tm, std::vector<Cand> &acc, bool &selected, int &rounds) {
+    rounds = 0;
+    selected = false;
+    tm.mark(9, s);
+    tm.mark(10, s);
+    if (p.N == 0) return PMP_OK;
+    std::vector<float> dir((size_t)p.L * kFD);
+    if (o.sieve_w > 0) {
+        // one Gaussian direction per length from the projections' stream (row 32,
+        // past the signature rows)
+        for (int l = 0; l < p.L; ++l)
+            for (int c = 0; c < kFD; ++c) dir[(size_t)l * kFD + c] = (float)gauss(o.seed, p.ms[l], 32, c);
+        HIPCHK(hipMemcpyAsync(b.sdir, dir.data(), dir.size() * sizeof(float), hipMemcpyHostToDevice,
+                              s));
+        const int rc = run_sieve(p, b, q, o, s);
+        if (rc) return rc;
+    }
+    tm.mark(9, s);
+    if (o.stride == 1) {
+        tm.mark(10, s);
+        return PMP_OK;
+    }
+    launch_hints(o.precision, q, p.nhint_blocks, s);
+    tm.mark(10, s);
+    if (o.compl_rounds == 0) return PMP_OK;
+    std::vector<uint32_t> seeds;
+    std::vector<Cand> prev;
+    unsigned long long improved = 1;
+    for (int r = 0; r <= o.compl_rounds; ++r) {
+        const int rc = select_topk(p, b, k, s, acc);   // also completes the copy of `improved`
+        if (rc) return rc;
+        selected = true;
+        // stop once a round lowers no cell or leaves the selected cells and
+        // their values as they were (later rounds would only re-verify), or
+        // when the k-th value is already 0, which no completion can lower
+        bool same = r > 0 && prev.size() == acc.size();
+        for (size_t x = 0; same && x < acc.size(); ++x)
+            same = prev[x].k == acc[x].k && prev[x].d == acc[x].d;
+        if (r == o.compl_rounds || improved == 0 || acc.empty() || same) break;
+        if (acc.size() == (size_t)k && acc.back().d == 0.0) break;
+        prev = acc;
+        seeds.resize(acc.size());
+        for (size_t x = 0; x < acc.size(); ++x) seeds[x] = acc[x].k;
+        HIPCHK(hipMemcpyAsync(b.seeds, seeds.data(), seeds.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, s));
+        launch_fill_u64((uint64_t *)&b.counters[C_COMPL_IMPROVED], 1, 0ull, s);
+        launch_complete(o.precision, q, b.seeds, (int)seeds.size(), o.compl_dm, o.compl_dp, s);
+        HIPCHK(hipMemcpyAsync(&improved, &b.counters[C_COMPL_IMPROVED], sizeof(improved),
+                              hipMemcpyDeviceToHost, s));
+        selected = false;
+        ++rounds;
+    }
+    return PMP_OK;
+}
+
+// ------------------------------------------------------------- pipeline
 
 static int check_args(int64_t n, int m_min, int m_max, int k, int excl, int budget) {
     if (n < 3) return fail(PMP_EINVAL, "series must have at least 3 samples");
@@ -608,7 +755,7 @@ static size_t upper_bytes(int64_t n, int m_min, int m_max, const Opt &o, int k) 
     a.sizing = true;
     Bufs b;
     carve1(a, b, p, k);
-    carve2(a, b, p, o.precision, k);
+    carve2(a, b, p, o, k);
     return a.off + 4096;
 }
 
@@ -724,7 +871,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     }
     plan_index(p, cnt, o, R.budget, K);
     if (p.N != (int64_t)toff[p.ntiles]) return fail(PMP_EINTERNAL, "index count mismatch");
-    carve2(ar, b, p, o.precision, R.k);
+    carve2(ar, b, p, o, R.k);
     if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
     const int64_t N = p.N;
 
@@ -776,6 +923,8 @@ static int run_pipeline(Run &R, Arena &ar) {
     q.emax = b.emax;
     q.counters = b.counters;
     q.bad = b.bad;
+    q.kmap = b.kmap;
+    q.hint = b.hint;
 
     // ---- one sketch pass, buckets
     std::vector<int64_t> bbase;             // lives until the call ends (async copy)
@@ -804,9 +953,10 @@ static int run_pipeline(Run &R, Arena &ar) {
     }
     launch_bucket_bounds(q, N, p.nbuckets, b.bstart, s);
     launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
+    launch_fill_u32(b.hint, N, kNone, s);
     tm.mark(3, s);
     tm.mark(4, s);
-    launch_probe(o.precision, q, b.bstart, N, p.max_m, s);
+    launch_probe(o.precision, q, b.bstart, p.nprobe_blocks, p.max_m, s);
     tm.mark(5, s);
     HIPCHK(hipGetLastError());
 
@@ -817,14 +967,22 @@ static int run_pipeline(Run &R, Arena &ar) {
                                b.cell, N, b.P, 0, (uint64_t *)R.dbg->profile_pass);
     }
 
-    // ---- selection on the upper profile; the flag of unrepresentable
-    // windows and the largest feature errors come back with it
+    // ---- emit stage (Sec. 3.6, Algorithm 2); the flag of unrepresentable
+    // windows and the largest feature errors come back with the first
+    // selection
     std::vector<float> emax(p.L);
     HIPCHK(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
     std::vector<Cand> acc;
-    int rc = select_topk(p, b, R.k, s, acc);
+    int crounds = 0;
+    bool selected = false;
+    int rc = emit_stage(p, b, q, o, R.k, s, tm, acc, selected, crounds);
     if (rc) return rc;
+    tm.mark(8, s);
+    if (!selected) {
+        rc = select_topk(p, b, R.k, s, acc);
+        if (rc) return rc;
+    }
     if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
@@ -1026,16 +1184,24 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->join_candidates = ctr[C_JOIN_CAND];
         st->join_verified = ctr[C_JOIN_VER];
         st->join_pairs = ctr[C_JOIN_PAIRS];
+        st->sieve_verified = ctr[C_SIEVE_VER];
+        st->hint_verified = ctr[C_HINT_VER];
+        st->complete_verified = ctr[C_COMPL_VER];
+        st->complete_rounds = crounds;
+        st->anchors = p.anchors;
         st->hot_buckets = ctr[C_HOT];
         st->max_depth = p.max_depth;
         st->threshold = T;
         st->ms_total = tm.ms(0, 7);
         st->ms_onepass = tm.ms(0, 5);
-        st->ms_certify = tm.ms(5, 7);
+        st->ms_certify = tm.ms(8, 7);
+        st->ms_complete = tm.ms(5, 8);
+        st->ms_sieve = tm.ms(5, 9);
+        st->ms_hints = tm.ms(9, 10);
         st->ms_sketch = tm.ms(1, 2);
         st->ms_sort = tm.ms(2, 3);
         st->ms_probe = tm.ms(4, 5);
-        st->ms_join = tm.ms(5, 6);
+        st->ms_join = tm.ms(8, 6);
         st->ms_rows = tm.ms(6, 7);
         st->workspace_bytes = ar.off;
     }
@@ -1137,6 +1303,11 @@ void pmp_default_options(pmp_options *o) {
     o->gamma = d.gamma;
     o->probe_ref_depth = d.d0;
     o->probe_cap = d.probe_cap;
+    o->anchor_stride = d.stride;
+    o->sieve_width = d.sieve_w;
+    o->complete_rounds = d.compl_rounds;
+    o->complete_dm = d.compl_dm;
+    o->complete_dp = d.compl_dp;
 }
 
 const char *pmp_last_error(void) { return g_err.c_str(); }

@@ -30,7 +30,10 @@ class Options(C.Structure):
     _fields_ = [("size", C.c_uint32), ("m_step", C.c_int32), ("precision", C.c_int32),
                 ("spectral_width", C.c_int32), ("seed", C.c_uint64), ("certify", C.c_int32),
                 ("signature_bits", C.c_int32), ("gamma", C.c_int32),
-                ("probe_ref_depth", C.c_int32), ("probe_cap", C.c_int32), ("reserved", C.c_int32)]
+                ("probe_ref_depth", C.c_int32), ("probe_cap", C.c_int32),
+                ("anchor_stride", C.c_int32), ("sieve_width", C.c_int32),
+                ("complete_rounds", C.c_int32), ("complete_dm", C.c_int32),
+                ("complete_dp", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -43,7 +46,11 @@ class Stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_onepass", C.c_double), ("ms_certify", C.c_double),
                 ("ms_sketch", C.c_double), ("ms_sort", C.c_double), ("ms_probe", C.c_double),
                 ("ms_join", C.c_double), ("ms_rows", C.c_double),
-                ("workspace_bytes", C.c_uint64), ("join_pairs", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("join_pairs", C.c_uint64),
+                ("sieve_verified", C.c_uint64), ("hint_verified", C.c_uint64),
+                ("complete_verified", C.c_uint64), ("ms_complete", C.c_double),
+                ("complete_rounds", C.c_int32), ("anchors", C.c_int32),
+                ("ms_sieve", C.c_double), ("ms_hints", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("size", "reserved")}

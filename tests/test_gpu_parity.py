@@ -336,12 +336,60 @@ def test_result_independent_of_width_budget_seed_precision(gpu, ws, oracle):
     ref = oracle.topk(rows, 20)
     for kw in [dict(spectral_width=4), dict(spectral_width=8), dict(spectral_width=16),
                dict(seed=1), dict(seed=99), dict(precision=1), dict(precision=2),
-               dict(signature_bits=8), dict(gamma=1), dict(probe_cap=0)]:
+               dict(signature_bits=8), dict(gamma=1), dict(probe_cap=0),
+               dict(anchor_stride=1), dict(anchor_stride=2), dict(anchor_stride=3),
+               dict(sieve_width=8), dict(complete_rounds=0), dict(sieve_width=8, complete_rounds=0),
+               dict(anchor_stride=4, sieve_width=32, complete_rounds=1, complete_dm=0,
+                    complete_dp=0)]:
         for budget in (4, 16, 64):
             res, _ = run(gpu, ws, t, 40, 70, 40, budget=budget, m_step=5, **kw)
             ok, msg = parity.check_topk(res, rows, 20, oracle, t, excl=40)
             assert ok, (kw, budget, msg)
             assert [(r.i, r.m) for r in res] == [(x.i, x.m) for x in ref]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_emit_stage_does_its_work_and_keeps_the_result(gpu, ws, oracle, prec):
+    """Anchors (Sec. 3.3): with stride 2 only every second length is probed,
+    the lengths between are re-cut from their anchors' hints, local
+    completion runs around the top cells, and the hot-class sieve (Sec. 3.6)
+    verifies the over-budget buckets; the exact top-k is the golden's in
+    every configuration, and dense indexing probes more."""
+    g = golden("tiny_top20")
+    t = golden_series(g)
+    stats = {}
+    for name, kw in (("dense", dict(anchor_stride=1)), ("s2", dict(anchor_stride=2, sieve_width=8)),
+                     ("s6", dict(anchor_stride=6)), ("no_emit", dict(anchor_stride=2,
+                                                                     sieve_width=0,
+                                                                     complete_rounds=0))):
+        res, st = run(gpu, ws, t, g["m_min"], g["m_max"], g["exclusion"], g["k"], gamma=1,
+                      precision=PRECS[prec], **kw)
+        ok, msg = parity.canonical_equal(res, g["top"])
+        assert ok, (name, msg)
+        stats[name] = st
+    L = g["m_max"] - g["m_min"] + 1
+    assert stats["dense"]["anchors"] == L and stats["dense"]["hint_verified"] == 0
+    assert stats["dense"]["complete_rounds"] == 0
+    assert stats["s2"]["anchors"] == (L + 1) // 2 + (0 if (L - 1) % 2 == 0 else 1)
+    assert stats["s2"]["hint_verified"] > 0 and stats["s2"]["complete_rounds"] >= 1
+    assert stats["s2"]["complete_verified"] > 0
+    assert stats["s2"]["pass_candidates"] < stats["dense"]["pass_candidates"]
+    assert stats["s6"]["pass_candidates"] < stats["s2"]["pass_candidates"]
+    # gamma = 1 makes R = 16, so the planted repeats overflow their buckets
+    assert stats["s2"]["hot_buckets"] > 0 and stats["s2"]["sieve_verified"] > 0
+    assert stats["no_emit"]["sieve_verified"] == 0 and stats["no_emit"]["complete_verified"] == 0
+
+
+def test_sieve_on_wafer_like_duplicates(gpu, ws):
+    """Wafer-like data puts thousands of exact repeats in one bucket: the
+    sieve verifies its members against their projection neighbours, and the
+    exact top-k stays the golden's with a small budget R."""
+    g = golden("wafer100k_top20")
+    t = golden_series(g)
+    res, st = run(gpu, ws, t, 50, 100, 50, 20, gamma=1, sieve_width=8)
+    ok, msg = parity.canonical_equal(res, g["top"])
+    assert ok, msg
+    assert st["hot_buckets"] > 0 and st["sieve_verified"] > 0
 
 
 def test_bitwise_repeatable(gpu, ws):
