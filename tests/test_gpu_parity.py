@@ -82,72 +82,24 @@ def test_wafer5m_full_size(gpu, ws, oracle):
         assert oracle.snap(oracle.distance(t, r.m, r.i, r.j)) == r.dist
 
 
-_ECG_ROWS: dict = {}                 # oracle rows of the ECG-like 1M series, by (m, start)
-
-
-def _ecg_rows(oracle, t, m, excl, starts):
-    """Exact (P, I) of cells of one length, computed once per cell."""
-    need = sorted({int(i) for i in starts} - {i for (mm, i) in _ECG_ROWS if mm == m})
-    if need:
-        P, I = oracle.cells(t, m, excl, need)
-        for i, p, j in zip(need, P.tolist(), I.tolist()):
-            _ECG_ROWS[(m, i)] = (oracle.snap(p), int(j))
-    return [_ECG_ROWS[(m, int(i))] for i in starts]
-
-
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_ecg1m_full_size(gpu, ws, oracle, prec):
+def test_ecg1m_full_size(gpu, ws, prec):
     """The precision-form workload at full size (ECG-like, 1M samples, m =
-    100..400 step 6, exclusion 100, top-20), as the benchmark runs it.  The
-    full profile is out of the oracle's reach here, so: every reported cell
-    is checked against its exact row (P, and I up to ties), the list obeys
-    the greedy rule, and on sampled cells of every third length no cell below
-    the k-th value is left out unless an accepted cell before it in (P, m,
-    i) order suppresses it."""
-    n, excl, k = 1_000_000, 100, 20
-    t = synth.ecg_like(n, synth.SEED_ECG_1M)
-    lengths = list(range(100, 401, 6))
-    res, st = run(gpu, ws, t, 100, 400, excl, k, m_step=6, precision=PRECS[prec])
-    assert len(res) == k
-    keys = [(r.dist, r.m, r.i) for r in res]
-    assert keys == sorted(keys)
-    for m in sorted({r.m for r in res}):
-        _ecg_rows(oracle, t, m, excl, [r.i for r in res if r.m == m])
-    for x, r in enumerate(res):
-        assert r.m in lengths and abs(r.i - r.j) >= excl
-        assert not any(a.m == r.m and 2 * abs(a.i - r.i) <= r.m for a in res[:x])
-        p, j = _ecg_rows(oracle, t, r.m, excl, [r.i])[0]
-        print(f"ecg1m {prec} motif {x}: i={r.i} j={r.j} m={r.m} dist={r.dist!r} "
-              f"oracle={p!r} rel_err={abs(r.dist - p) / p if p else abs(r.dist):.3g}")
-        assert parity.dist_close(r.dist, p), (r, p)
-        if r.j != j:
-            assert parity.dist_close(oracle.snap(oracle.distance(t, r.m, r.i, r.j)), p), (r, j)
-    dk = res[-1].dist
-    rng = np.random.default_rng(2607)
-    # random cells of every third length, and the cells most likely to hold
-    # a missed motif: each reported start at the neighbouring lengths, and
-    # the first starts outside each reported cell's suppression zone
-    sample = {m: set(rng.choice(n - m + 1, size=8, replace=False).tolist()) for m in lengths[::3]}
-    for r in res:
-        for m2 in (r.m - 6, r.m + 6):
-            if m2 in lengths:
-                sample.setdefault(m2, set()).add(r.i)
-        for i2 in (r.i - r.m // 2 - 1, r.i + r.m // 2 + 1):
-            if 0 <= i2 <= n - r.m:
-                sample.setdefault(r.m, set()).add(i2)
-    checked = below = 0
-    for m in sorted(sample):
-        starts = sorted(sample[m])
-        for i, (p, _) in zip(starts, _ecg_rows(oracle, t, m, excl, starts)):
-            checked += 1
-            if not p < dk * (1 - parity.REL_DIST):
-                continue
-            below += 1
-            # a cell below the k-th value that was not accepted must be
-            # suppressed by an accepted cell of its length that precedes it
-            assert any(a.m == m and 2 * abs(a.i - i) <= m and (a.dist, a.m, a.i) < (p, m, i)
-                       for a in res), (m, i, p, dk)
-    print(f"ecg1m {prec}: {checked} sampled cells, {below} below the k-th value {dk:.6g}")
+    100..400 step 6, exclusion 100, top-20), as the benchmark runs it,
+    against the oracle's full profile (every cell of every length, by oracle
+    v2, which equals the brute force; the committed golden).  The distance
+    error of each reported motif against the oracle is printed."""
+    g = golden("ecg1m_top20")
+    t = golden_series(g)
+    res, st = run(gpu, ws, t, g["m_min"], g["m_max"], g["exclusion"], g["k"],
+                  m_step=g["m_step"], precision=PRECS[prec])
+    for x, (r, ref) in enumerate(zip(res, g["top"])):
+        rel = abs(r.dist - ref[3]) / ref[3] if ref[3] else abs(r.dist)
+        print(f"ecg1m {prec} motif {x}: gpu ({r.i}, {r.j}, {r.m}, {r.dist!r}) "
+              f"oracle {tuple(ref)} rel_err={rel:.3g}")
+    ok, msg = parity.canonical_equal(res, g["top"])
+    assert ok, msg
+    assert st["certify_rounds"] >= 1
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
