@@ -62,8 +62,13 @@ enum {
     PMP_PREC_FP32 = 1,  /* windows x DFT basis on the matrix cores, both
                            split exactly into three bf16 parts (six products,
                            FP32 accumulation): FP32-grade features           */
-    PMP_PREC_BF16 = 2   /* the same product in plain bf16 (one product,
-                           FP32 accumulation): a wider margin                */
+    PMP_PREC_BF16 = 2   /* BF16 keys + FP32 bound: the features, the bound and
+                           the join as in PMP_PREC_FP32; the SimHash
+                           projection of the keys in plain bf16 (one product
+                           instead of three).  Keys only steer candidates
+                           (Sec. 3.4, Prop. 2), so plain bf16 costs no
+                           validity; features computed from plain-bf16 inputs
+                           would make the bound's margin 2^8 times wider.   */
 };
 
 typedef struct {

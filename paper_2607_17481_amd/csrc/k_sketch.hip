@@ -496,7 +496,6 @@ __device__ __forceinline__ mbf16x8 u4_as_bf16x8(uint4 v) {
 }
 }  // namespace
 
-template <int kProducts>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_sketch_mfma(Req q, const uint32_t *__restrict__ E,
                                                         const uint32_t *__restrict__ tile_off,
                                                         const int64_t *__restrict__ bbase,
@@ -538,24 +537,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // The feature vector X / sigma is therefore within sqrt(K') m per.
     // per: y and B rounded to float (2 x 2^-24) and the FP64 centring and
     // chunk sums ((m / 8 + 4) u64); then, with u = 2^-8 the bf16 unit
-    // roundoff and every FP32 addition rounding by up to 2^-23,
-    //   form 1: mid.lo + lo.mid + lo.lo <= (2 (1 + u) u^3 + u^4) < 2^-23
-    //     (|mid| <= (1 + u) u |y|, |lo| <= u^2 |y|); hi.hi summed from zero
-    //     per chunk of 16 samples (16 additions over products within (1 +
-    //     u)^2 of |y_r B_r|); the other five products, together below 1.03
-    //     x 2^-7 of |y_r B_r|, summed from zero over groups of 4 chunks
-    //     (320 additions);
-    //   form 2: the bf16 roundings of y and B, u + (1 + u) u = 2u + u^2,
-    //     and 16 additions.
+    // roundoff and every FP32 addition rounding by up to 2^-23:
+    // mid.lo + lo.mid + lo.lo <= (2 (1 + u) u^3 + u^4) < 2^-23 (|mid| <=
+    // (1 + u) u |y|, |lo| <= u^2 |y|); hi.hi summed from zero per chunk of 16
+    // samples (16 additions over products within (1 + u)^2 of |y_r B_r|);
+    // the other five products, together below 1.03 x 2^-7 of |y_r B_r|,
+    // summed from zero over groups of 4 chunks (320 additions).
     // The float and bf16 values of normal-range samples are exact splits;
     // flushed subnormals (the parts, products and partial sums of one
     // sample, at most 16 of them) add at most 2^-122 per sample in absolute
     // terms, counted separately below.
-    const double per = 2.0 * 0x1.0p-24 + ((double)m / 8.0 + 4.0) * u64 +
-                       (kProducts == 6 ? 0x1.0p-23 * 1.01 + 16.0 * 0x1.0p-23 * 1.01 +
-                                             320.0 * 0x1.0p-23 * 1.03 * 0x1.0p-7 * 1.01
-                                       : (2.0 * 0x1.0p-8 + 0x1.0p-16) * 1.01 +
-                                             16.0 * 0x1.0p-23 * 1.02);
+    const double per = 2.0 * 0x1.0p-24 + ((double)m / 8.0 + 4.0) * u64 + 0x1.0p-23 * 1.01 +
+                       16.0 * 0x1.0p-23 * 1.01 + 320.0 * 0x1.0p-23 * 1.03 * 0x1.0p-7 * 1.01;
     const double ecomp = sqrt((double)L.kprime) * per * (double)m * (1.0 + 1e-6);
     const double eabs = sqrt(2.0 * L.kprime) * (double)m * 0x1.0p-122;
     float emax = 0.0f;
@@ -574,21 +567,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // B operands of feature i, samples r0 + 8 hh .. + 7: loaded one chunk
         // ahead
         int bo = (i * mp + 8 * hh) / 8;
-        uint4 nbh = Bh[bo], nbm = nbh, nbl = nbh;
-        if (kProducts == 6) {
-            nbm = Bm[bo];
-            nbl = Bl[bo];
-        }
+        uint4 nbh = Bh[bo], nbm = Bm[bo], nbl = Bl[bo];
         for (int r0 = 0; r0 < mp; r0 += 16) {
             const mbf16x8 bhv = u4_as_bf16x8(nbh);
             const mbf16x8 bmv = u4_as_bf16x8(nbm), blv = u4_as_bf16x8(nbl);
             if (r0 + 16 < mp) {
                 bo += 2;
                 nbh = Bh[bo];
-                if (kProducts == 6) {
-                    nbm = Bm[bo];
-                    nbl = Bl[bo];
-                }
+                nbm = Bm[bo];
+                nbl = Bl[bo];
             }
             // A: window i, the same samples (centred, split by the
             // hardware's round-to-nearest-even conversion of the float
@@ -604,30 +591,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             mbf16x8 ah, am, al;
 #pragma unroll
             for (int e = 0; e < 8; ++e) ah[e] = (__bf16)yf[e];
-            if (kProducts == 6) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    yf[e] -= (float)ah[e];                                // exact
-                    am[e] = (__bf16)yf[e];
-                }
-#pragma unroll
-                for (int e = 0; e < 8; ++e) al[e] = (__bf16)(yf[e] - (float)am[e]);   // exact
+            for (int e = 0; e < 8; ++e) {
+                yf[e] -= (float)ah[e];                                    // exact
+                am[e] = (__bf16)yf[e];
             }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) al[e] = (__bf16)(yf[e] - (float)am[e]);   // exact
             mf32x16 acc = {};
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhv, acc, 0, 0, 0);
-            if (kProducts == 6) {
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bmv, acc2, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bhv, acc2, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc2, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc2, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bmv, acc2, 0, 0, 0);
-                // the smaller products go to FP64 every 4 chunks
-                if ((r0 & 63) == 48 || r0 + 16 >= mp) {
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bmv, acc2, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bhv, acc2, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blv, acc2, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhv, acc2, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bmv, acc2, 0, 0, 0);
+            // the smaller products go to FP64 every 4 chunks
+            if ((r0 & 63) == 48 || r0 + 16 >= mp) {
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        sum[v] += (double)acc2[v];
-                        acc2[v] = 0.0f;
-                    }
+                for (int v = 0; v < 16; ++v) {
+                    sum[v] += (double)acc2[v];
+                    acc2[v] = 0.0f;
                 }
             }
 #pragma unroll
@@ -692,7 +675,7 @@ struct KeysSmem {
 
 }  // namespace
 
-template <typename FT>
+template <typename FT, bool kBf16Keys>
 __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict__ gproj) {
     __shared__ KeysSmem sm;
     int l;
@@ -819,8 +802,9 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
     // ---- SimHash projections <g_b, G> of the wavefront's 64 windows on the
     // matrix cores: two blocks of 32 windows x 32 bits (B used) over 32
     // features (30 used), split bf16 (hi.hi + hi.lo + lo.hi, FP32 sums;
-    // within about 2^-16 |g| |f| of the FP32 dot, where bits near zero may
-    // flip -- keys steer candidates only, never validity).  Operand A of a
+    // within about 2^-16 |g| |f| of the FP32 dot), or with the BF16 keys of
+    // precision form 2, hi.hi alone (within about 2^-7); bits near zero may
+    // flip either way -- keys steer candidates only, never validity.  Operand A of a
     // block: lane L holds window (L mod 32) of the block and features
     // 8 (L / 32) .. +8 of each 16-feature slice; a lane's other half comes
     // from its partner L ^ 32.
@@ -851,8 +835,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
             const mbf16x8 bh = u4_as_bf16x8(*(const uint4 *)&sm.gh[col][16 * sl + koff]);
             const mbf16x8 bl = u4_as_bf16x8(*(const uint4 *)&sm.gl[col][16 * sl + koff]);
             c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, bh, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, bl, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, bh, c, 0, 0, 0);
+            if (!kBf16Keys) {
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, bl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, bh, c, 0, 0, 0);
+            }
         }
         // to LDS: register r of lane L is row 8 (r / 4) + 4 (L / 32) + r % 4,
         // column L mod 32
@@ -965,20 +951,24 @@ void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const ui
                         const uint16_t *bm, const uint16_t *bl, hipStream_t s) {
     // samples of the tile, padded with zeros for the last block's reads
     const size_t dyn = (size_t)(kTileW + ((max_m + 15) & ~15) + kMBlk) * sizeof(double);
-    if (precision == 1)
-        hipLaunchKernelGGL((k_sketch_mfma<6>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, bbase, bh, bm, bl);
-    else
-        hipLaunchKernelGGL((k_sketch_mfma<1>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                           tile_off, bbase, bh, bm, bl);
+    // both precision forms take FP32-grade features (form 2 differs in its
+    // keys only)
+    (void)precision;
+    hipLaunchKernelGGL(k_sketch_mfma, dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
+                       tile_off, bbase, bh, bm, bl);
 }
 
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s) {
     if (nblocks <= 0) return;
     if (precision == 0)
-        hipLaunchKernelGGL(k_keys<double>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj);
+        hipLaunchKernelGGL((k_keys<double, false>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, q,
+                           q.gproj);
+    else if (precision == 1)
+        hipLaunchKernelGGL((k_keys<float, false>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, q,
+                           q.gproj);
     else
-        hipLaunchKernelGGL(k_keys<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, q, q.gproj);
+        hipLaunchKernelGGL((k_keys<float, true>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, q,
+                           q.gproj);
 }
 
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,

@@ -192,6 +192,8 @@ def test_moments_features_keys(gpu, ws, oracle, prec):
         np.testing.assert_allclose(sig[base:base + W][~ocst], osig[~ocst], rtol=1e-12)
         assert np.array_equal(sig[base:base + W] == 0.0, ocst)
         assert host["indexed"][li] == int((~ocst).sum())
+        gproj = np.array([[oracle.projection(seed, m, b, c) for c in range(30)]
+                          for b in range(24)])
         # a2: features within the bound the library derives for them
         for i in rng.choice(np.nonzero(~ocst)[0], size=300, replace=False):
             fo = oracle.features(t, m, int(i), 16)
@@ -206,16 +208,24 @@ def test_moments_features_keys(gpu, ws, oracle, prec):
             assert F[base + i, 31] >= (np.linalg.norm(fo) - e_i) * (1 - 1e-6)
             if prec == "fp64":
                 assert err <= 1e-9 * m
-            if prec == "fp32":
-                # FP32-grade features, and a bound of the same order
+            if prec in ("fp32", "bf16"):
+                # FP32-grade features in both precision forms (form 2 differs
+                # in its keys only), and a bound of the same order
                 # (sqrt(K') m per, per about 18 x 2^-23)
                 assert err <= 1e-5 * np.linalg.norm(fo), (m, i, err)
                 assert e_i <= 2e-5 * m, (m, i, e_i)
-            # a3: signature bits where the margin clears the FP32 key error
+            # a3: signature bits where the margin clears the key error: the
+            # split-bf16 projection of the FP32 copy (about 2^-16 |g| |f|),
+            # or in form 2 the plain bf16 one (2^-7 sum |g_c f_c|, bf16
+            # rounding of both operands, plus FP32 sums)
             sig_o, marg = oracle.signature(fo, 16, m, 24, seed)
             kw = int(keys[base + i])
-            tol = 1e-5 * np.linalg.norm(fo) * 6.0 + 2 * e_i * 6.0
             for b in range(24):
+                if prec == "bf16":
+                    tol = (2.0 ** -7 * 1.05 * float(np.abs(gproj[b]) @ np.abs(fo))
+                           + 2 * e_i * float(np.linalg.norm(gproj[b])) + 1e-6)
+                else:
+                    tol = 1e-5 * np.linalg.norm(fo) * 6.0 + 2 * e_i * 6.0
                 if abs(marg[b]) > tol:
                     assert ((kw >> (23 - b)) & 1) == ((sig_o >> (23 - b)) & 1), (m, i, b)
         assert np.all(keys[base:base + W][ocst] == np.uint64(0xFFFFFFFFFFFFFFFF))
