@@ -240,6 +240,7 @@ __global__ __launch_bounds__(kWave) void k_pca(const double *__restrict__ cov, i
 // resolution of the two-coordinate grid.
 __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__restrict__ gl,
                                                       int64_t N, int cb1, int cb2, int cb3,
+                                                      int l_lim, int64_t i_lim,
                                                       uint32_t *__restrict__ gkey,
                                                       uint32_t *__restrict__ gval,
                                                       uint8_t *__restrict__ qf,
@@ -261,7 +262,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
     gkey[k] = ((uint32_t)l << (cb1 + cb2 + cb3)) | (cell(p1, cb1, G.hinv) << (cb2 + cb3)) |
               (cb2 ? cell(p2, cb2, G.hinv2) << cb3 : 0u) | (cb3 ? cell(p3, cb3, G.hinv2) : 0u);
     gval[k] = (uint32_t)k;
-    const bool f = q.P[k] != 0ull;
+    // a query: a cell not yet at 0 whose (length, start) lies at or before
+    // the bound (the bound is the last length when it does not apply)
+    const int64_t i = (int64_t)q.cell[k] - q.len[l].cell_base;
+    const bool f = q.P[k] != 0ull && (l < l_lim || (l == l_lim && i <= i_lim));
     qf[k] = f;
     // the same flag in the sign of the candidate's Gram term, so that a
     // candidate tile reads one 16-byte word per window besides its operands
@@ -595,11 +599,11 @@ void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hi
 }
 
 void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2, int cb3,
-                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
-                      hipStream_t s) {
+                      int l_lim, int64_t i_lim, uint32_t *gkey, uint32_t *gval, uint8_t *qf,
+                      float4 *gp, hipStream_t s) {
     if (N <= 0) return;
     hipLaunchKernelGGL(k_grid_keys, dim3(nblk(N)), dim3(kBlock), 0, s, q, gl, N, cb1, cb2, cb3,
-                       gkey, gval, qf, gp);
+                       l_lim, i_lim, gkey, gval, qf, gp);
 }
 
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,

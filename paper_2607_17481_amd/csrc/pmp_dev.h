@@ -482,10 +482,12 @@ void launch_select(const uint64_t *P, int64_t n, int64_t need, SelState *st,
 size_t join_cov_doubles(int L);
 // principal directions: covariance of a sample, then power iteration (GPU)
 void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s);
-// grid keys over cb1 (and cb2, cb3 when nonzero) bits of the principal coordinates
+// grid keys over cb1 (and cb2, cb3 when nonzero) bits of the principal
+// coordinates, of the first N indexed windows; queries are the cells not at 0
+// with (length, start) <= (l_lim, i_lim)
 void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2, int cb3,
-                      uint32_t *gkey, uint32_t *gval, uint8_t *qf, float4 *gp,
-                      hipStream_t s);
+                      int l_lim, int64_t i_lim, uint32_t *gkey, uint32_t *gval, uint8_t *qf,
+                      float4 *gp, hipStream_t s);
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
                        const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,

@@ -673,9 +673,11 @@ static int run_sieve(const Plan &p, Bufs &b, const Req &q, const Opt &o, hipStre
 
 // Sieve, hints at the lengths between anchors, then local completion around
 // the current top-k for up to P_max rounds, each round's seeds re-selected,
-// until a round lowers no cell.  `selected`: `acc` holds the selection of the
-// final upper profile (otherwise the caller selects); `rounds`: completion
-// rounds run.
+// until a round lowers no cell.  When the k-th cell accepted before the hints
+// is at 0, only zeros ordered before it -- at shorter lengths -- can change
+// the top-k, so only those lengths get hints, and no completion runs (it
+// cannot lower a 0).  `selected`: `acc` holds the selection of the final upper
+// profile (otherwise the caller selects); `rounds`: completion rounds run.
 static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipStream_t s,
                       Timer &tm, std::vector<Cand> &acc, bool &selected, int &rounds) {
     rounds = 0;
@@ -699,9 +701,21 @@ static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipSt
         tm.mark(10, s);
         return PMP_OK;
     }
-    launch_hints(o.precision, q, p.nhint_blocks, s);
+    {
+        const int rc = select_topk(p, b, k, s, acc);
+        if (rc) return rc;
+        selected = true;
+    }
+    const bool zero_kth = acc.size() == (size_t)k && acc.back().d == 0.0;
+    // hint blocks follow the lengths' order: those of the lengths before the
+    // k-th cell's come first
+    const int64_t hint_blocks = zero_kth ? p.len[acc.back().l].hblk_base : p.nhint_blocks;
+    if (hint_blocks > 0) {
+        launch_hints(o.precision, q, hint_blocks, s);
+        selected = false;
+    }
     tm.mark(10, s);
-    if (o.compl_rounds == 0) return PMP_OK;
+    if (o.compl_rounds == 0 || zero_kth) return PMP_OK;
     std::vector<uint32_t> seeds;
     std::vector<Cand> prev;
     unsigned long long improved = 1;
@@ -987,6 +1001,26 @@ static int run_pipeline(Run &R, Arena &ar) {
     int rounds = 0;
     double T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
     if (R.dbg && R.dbg->t_start_scale > 0.0 && std::isfinite(T)) T *= R.dbg->t_start_scale;
+    // The greedy's first k acceptances depend only on the cells whose exact
+    // key (P, m, i) lies at or before the k-th accepted one: those that reach
+    // it from a cell the join left inexact have upper values no lower than
+    // their exact ones.  So each round makes exact every cell whose key may
+    // lie at or below the bound (T, l_lim, i_lim): while T > 0 every cell at
+    // or below T, whatever its start; at T = 0 only the zeros at or before the
+    // k-th accepted cell in (length, start) order -- the join's queries and
+    // its lengths stop there.  The round is the last once the k-th accepted
+    // key after it lies within the bound.
+    int l_lim = p.L - 1;
+    int64_t i_lim = INT64_MAX;
+    auto set_bound = [&]() {
+        l_lim = p.L - 1;
+        i_lim = INT64_MAX;
+        if (acc.size() == (size_t)R.k && T == 0.0) {
+            l_lim = acc.back().l;
+            i_lim = acc.back().i;
+        }
+    };
+    set_bound();
     if (o.certify && N > 0) {
         std::vector<GridLen> gl(p.L);
         int64_t ntiles = 0;
@@ -1056,17 +1090,30 @@ static int run_pipeline(Run &R, Arena &ar) {
                 G.sqrt2m = (float)std::sqrt(2.0 / m) * (1.0f + 1e-7f);
             }
             HIPCHK(hipMemcpyAsync(b.gl, gl.data(), p.L * sizeof(GridLen), hipMemcpyHostToDevice, s));
-            launch_grid_keys(q, b.gl, N, cb1, cb2, cb3, b.jk, b.jv, b.qf, b.gp, s);
-            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, N, 0, p.len_bits + cb1 + cb2 + cb3, b.sort_tmp,
-                             s);
-            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntiles,
+            // windows and tiles of the lengths up to the bound (sorted by
+            // length first, so they are a prefix)
+            const int64_t Nq = p.len[l_lim].kbase + p.len[l_lim].n_index;
+            const int64_t ntq =
+                gl[l_lim].tile_base + (p.len[l_lim].n_index + kJoinTile - 1) / kJoinTile;
+            launch_grid_keys(q, b.gl, Nq, cb1, cb2, cb3, l_lim, i_lim, b.jk, b.jv, b.qf, b.gp, s);
+            radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, Nq, 0, p.len_bits + cb1 + cb2 + cb3,
+                             b.sort_tmp, s);
+            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntq,
                               cb1, cb2, cb3, Teff, s);
             HIPCHK(hipGetLastError());
             rc = select_topk(p, b, R.k, s, acc);   // synchronizes: gl may be rewritten next
             if (rc) return rc;
             if (std::isinf(T)) break;                               // exhaustive
-            if (acc.size() == (size_t)R.k && acc.back().d <= T) break;
-            T = acc.size() == (size_t)R.k ? acc.back().d : INFINITY;
+            if (acc.size() == (size_t)R.k) {
+                const Cand &c = acc.back();
+                const bool within = c.d < T || (c.d == T && (T > 0.0 || c.l < l_lim ||
+                                                             (c.l == l_lim && c.i <= i_lim)));
+                if (within) break;
+                T = c.d;
+            } else {
+                T = INFINITY;
+            }
+            set_bound();
             if (rounds > 64) return fail(PMP_EINTERNAL, "threshold join did not converge");
         }
     }

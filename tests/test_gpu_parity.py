@@ -354,6 +354,30 @@ def test_sieve_on_wafer_like_duplicates(gpu, ws):
     assert st["hot_buckets"] > 0 and st["sieve_verified"] > 0
 
 
+_ZERO_ROWS: dict = {}
+
+
+@pytest.mark.parametrize("prec,stride", [("fp64", 6), ("fp64", 1), ("fp32", 6), ("bf16", 3)])
+def test_zero_kth_value_spanning_lengths(gpu, ws, oracle, prec, stride):
+    """Exact repeats (affine copies, distance 0) short enough that the zeros
+    accepted at the shortest length run out: the k-th accepted cell is a 0 at
+    the third length.  With a k-th value of 0 the certificate only has to
+    settle the zeros ordered before that cell, (m, i) <= (m_k, i_k), and the
+    hints only the lengths before m_k; the top-k must still be the oracle's."""
+    rng = np.random.default_rng(31)
+    t = np.cumsum(rng.standard_normal(3000))
+    pat = t[200:230].copy()
+    for a, sc, off in ((900, 2.0, 5.0), (1700, 0.5, -3.0), (2500, 1.0, 10.0)):
+        t[a:a + 30] = sc * pat + off
+    if not _ZERO_ROWS:
+        _ZERO_ROWS.update(oracle.pan_profile_v2(t, range(16, 41), 60))
+    ref = oracle.topk(_ZERO_ROWS, 20)
+    assert ref[-1].dist == 0.0 and ref[-1].m == 18
+    res, st = run(gpu, ws, t, 16, 40, 60, 20, precision=PRECS[prec], anchor_stride=stride)
+    ok, msg = parity.check_topk(res, _ZERO_ROWS, 20, oracle, t, excl=60)
+    assert ok, msg
+
+
 def test_bitwise_repeatable(gpu, ws):
     t = synth.wafer_like(50000, seed=8, copies=5)
     a, _ = run(gpu, ws, t, 50, 70, 50)
