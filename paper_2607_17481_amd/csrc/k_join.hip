@@ -272,6 +272,23 @@ __global__ __launch_bounds__(kBlock) void k_grid_keys(Req q, const GridLen *__re
     gp[k].w = f ? -fabsf(c.w) : fabsf(c.w);
 }
 
+// The join operands and coordinates in sorted (grid) order, so that a tile
+// of the order reads one contiguous block, with no index load before it.
+__global__ __launch_bounds__(kBlock) void k_join_gather(const uint32_t *__restrict__ gval,
+                                                        const uint4 *__restrict__ jop,
+                                                        const float4 *__restrict__ gp, int64_t n,
+                                                        uint4 *__restrict__ jop_s,
+                                                        float4 *__restrict__ gp_s) {
+    // eight threads per window: one 16-byte part of its operands each
+    const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t pos = x >> 3;
+    const int part = (int)(x & 7);
+    if (pos >= n) return;
+    const uint32_t k = gval[pos];
+    jop_s[pos * 8 + part] = jop[(int64_t)k * 8 + part];
+    if (part == 0) gp_s[pos] = gp[k];
+}
+
 // ------------------------------------------------------------ the tiles
 
 // The exact stage of a tile's queued pairs (whole wavefront): each pair that
@@ -339,34 +356,39 @@ __device__ __forceinline__ uint2 join_exact(const double *__restrict__ t,
     return make_uint2(n_kept, n_ver);
 }
 
-// One wavefront per tile of 32 consecutive sorted windows of one length, and
-// one wavefront per block: tile costs vary widely, and a single-wave block
-// frees its slot (and its LDS queue) as soon as its own tile is done.
-constexpr int kJoinWaves = 1;
+// A block of kJB wavefronts takes kJB consecutive query tiles of 32 sorted
+// windows of one length.  It walks the candidate runs of the union of their
+// queries' neighbourhoods together, and each candidate tile is loaded once
+// by the whole block into LDS (double-buffered: the next tile's loads are in
+// flight while the current one goes through the matrix cores and the
+// filter) and read from there by every wavefront, so the kJB query tiles,
+// whose neighbourhoods nearly coincide, share its global traffic.  Every
+// wavefront keeps its own queries, filter terms and queue of kept pairs, and
+// runs the exact stage when its queue fills.
+constexpr int kJB = kJoinBlock;               // query tiles (wavefronts) per block
+constexpr int kJRow = 9;                      // uint4 per LDS operand row (8 + 1: no bank conflicts)
+
 template <typename FT>
-__global__ __launch_bounds__(kJoinWaves * kWave) __attribute__((amdgpu_waves_per_eu(2)))
-void k_join_tiles(Req q, const GridLen *__restrict__ gl,
-                                                       const uint32_t *__restrict__ gkey,
-                                                       const uint32_t *__restrict__ gval,
-                                                       const uint8_t *__restrict__ qf,
-                                                       const uint4 *__restrict__ jop,
-                                                       const float4 *__restrict__ jmeta,
-                                                       const float4 *__restrict__ gp,
-                                                       int64_t ntiles, int cb1, int cb2, int cb3,
-                                                       double T) {
-    __shared__ uint2 queue[kJoinWaves][kQueueCap];
-    __shared__ float roww[kJoinWaves][kJT];           // the queries' Gram filter terms
-    __shared__ float4 rowc[kJoinWaves][kJT];          // the queries' principal coordinates
-    const int wv = threadIdx.x / kWave;
+__global__ __launch_bounds__(kJB * kWave) __attribute__((amdgpu_waves_per_eu(2)))
+void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restrict__ gkey,
+                  const uint32_t *__restrict__ gval, const uint8_t *__restrict__ qf,
+                  const uint4 *__restrict__ jop_s, const float4 *__restrict__ jmeta,
+                  const float4 *__restrict__ gp_s, int cb1, int cb2, int cb3, double T) {
+    __shared__ uint2 queue[kJB][kQueueCap];
+    __shared__ float roww[kJB][kJT];                  // the queries' Gram filter terms
+    __shared__ float4 rowc[kJB][kJT];                 // the queries' principal coordinates
+    __shared__ uint4 cop[2][kJT][kJRow];              // candidate operands, two tiles
+    __shared__ float4 cgp[2][kJT];                    // candidate coordinates and Gram terms
+    __shared__ int red[2][kJB];                       // block reductions
+    const int tid = threadIdx.x;
+    const int wv = tid / kWave;
     const int lane = lane_id();
-    const int64_t tile = (int64_t)blockIdx.x * kJoinWaves + wv;
-    if (tile >= ntiles) return;
     int l;
     {
         int lo = 0, hi = q.L - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (gl[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+            if (gl[mid].blk_base <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
         }
         l = lo;
     }
@@ -374,18 +396,39 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
     const LenInfo L = q.len[l];
     const int m = L.m;
     const int64_t pbeg = L.kbase, pend = L.kbase + L.n_index;
-    const int64_t p0 = pbeg + (tile - G.tile_base) * kJT;
+    const int64_t p0 = pbeg + (((int64_t)blockIdx.x - G.blk_base) * kJB + wv) * kJT;
     const int i = lane % kJT, hh = lane / kJT;
     const int64_t pq = p0 + i;
     const bool validq = pq < pend;
     const uint32_t kq = validq ? gval[pq] : 0u;
     const bool isq = validq && qf[kq];
-    if (__ballot(isq) == 0) return;
+
+    // block-wide min and max of one wave-uniform value per wavefront
+    auto block_minmax = [&](int vmin, int vmax, int &omin, int &omax) {
+        if (lane == 0) {
+            red[0][wv] = vmin;
+            red[1][wv] = vmax;
+        }
+        __syncthreads();
+        omin = red[0][0];
+        omax = red[1][0];
+#pragma unroll
+        for (int w = 1; w < kJB; ++w) {
+            omin = min(omin, red[0][w]);
+            omax = max(omax, red[1][w]);
+        }
+        __syncthreads();
+    };
+    {
+        int none, anyq;
+        block_minmax(0, __ballot(isq) ? 1 : 0, none, anyq);
+        if (!anyq) return;                        // uniform over the block
+    }
 
     // ---- query operands (A) and filter terms
     bf16x8 aH0, aH1, aL0, aL1;
     {
-        const uint4 *o = jop + (int64_t)kq * 8;
+        const uint4 *o = jop_s + pq * 8;
         const uint4 z = make_uint4(0, 0, 0, 0);
         aH0 = as_bf16x8(isq ? o[hh] : z);
         aH1 = as_bf16x8(isq ? o[2 + hh] : z);
@@ -402,22 +445,21 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
     }
     if (hh == 0) {
         roww[wv][i] = a;
-        rowc[wv][i] = isq ? gp[kq] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        rowc[wv][i] = isq ? gp_s[pq] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
 
-    // ---- the rows of adjacent cells
+    // ---- the rows of adjacent cells, over the block's queries
     const uint32_t mask1 = (1u << cb1) - 1u, mask2 = (1u << cb2) - 1u, mask3 = (1u << cb3) - 1u;
     const uint32_t key_q = validq ? gkey[pq] : 0u;
     const int c1q = (int)((key_q >> (cb2 + cb3)) & mask1), c2q = (int)((key_q >> cb3) & mask2);
     const int c3q = (int)(key_q & mask3);
-    const int c1min = wave_min_i(isq ? c1q : INT_MAX), c1max = wave_max_i(isq ? c1q : -1);
+    int c1min, c1max;
+    block_minmax(wave_min_i(isq ? c1q : INT_MAX), wave_max_i(isq ? c1q : -1), c1min, c1max);
     const uint32_t lbits = (uint32_t)l << (cb1 + cb2 + cb3);
     unsigned long long n_pairs = 0, n_kept = 0, n_ver = 0;
-    int qn = 0;                                           // queued pairs (uniform)
+    int qn = 0;                                           // queued pairs (wave-uniform)
 
-    // exact stage for the queued pairs
+    // exact stage for the queued pairs of this wavefront
     auto flush = [&]() {
         // the queue is written and read by lanes of this wavefront only
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -431,17 +473,15 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
         qn = 0;
     };
 
-    // walk the candidate runs (one per grid row next to a query's cell) in
-    // tiles of 32.  The operands of the next tile are loaded before the
-    // current one goes through the matrix cores and the filter, so that their
-    // latency overlaps that work.  The exact stage runs whenever the queue
-    // passes kQueueHigh and once at the end (one call site).
+    // the block's candidate runs (one per grid row next to a query's cell);
+    // every decision below is uniform over the block, so that every
+    // wavefront passes the same barriers
     int c1p = max(c1min - 1, 0) - 1;
     const int c1end = min(c1max + 1, (int)mask1);
     int64_t c0 = 0, cend = 0;
     int c2p = 0, c2end = -1;                              // three coordinates: the row's c2 range
     // move [c0, cend) to the next non-empty run once the current one is used
-    // up (uniform); false when there is none
+    // up; false when there is none
     auto next_run = [&]() -> bool {
         if (cb3 > 0) {
             // three coordinates: one run per pair of adjacent (c1, c2) cells,
@@ -450,16 +490,20 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
                 if (c2p >= c2end) {
                     ++c1p;
                     const bool near1 = isq && abs(c1q - c1p) <= 1;
-                    if (__ballot(near1) == 0) continue;
-                    c2p = wave_min_i(near1 ? max(c2q - 1, 0) : INT_MAX) - 1;
-                    c2end = wave_max_i(near1 ? min(c2q + 1, (int)mask2) : -1);
+                    int lo2, hi2;
+                    block_minmax(wave_min_i(near1 ? max(c2q - 1, 0) : INT_MAX),
+                                 wave_max_i(near1 ? min(c2q + 1, (int)mask2) : -1), lo2, hi2);
+                    if (lo2 > hi2) continue;
+                    c2p = lo2 - 1;
+                    c2end = hi2;
                     continue;
                 }
                 ++c2p;
                 const bool near = isq && abs(c1q - c1p) <= 1 && abs(c2q - c2p) <= 1;
-                if (__ballot(near) == 0) continue;
-                const int c3lo = wave_min_i(near ? max(c3q - 1, 0) : INT_MAX);
-                const int c3hi = wave_max_i(near ? min(c3q + 1, (int)mask3) : -1);
+                int c3lo, c3hi;
+                block_minmax(wave_min_i(near ? max(c3q - 1, 0) : INT_MAX),
+                             wave_max_i(near ? min(c3q + 1, (int)mask3) : -1), c3lo, c3hi);
+                if (c3lo > c3hi) continue;
                 const uint32_t rk = lbits | ((uint32_t)c1p << (cb2 + cb3)) | ((uint32_t)c2p << cb3);
                 c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c3lo);
                 cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c3hi) + 1u);
@@ -477,9 +521,10 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
             while (c0 >= cend && c1p < c1end) {
                 ++c1p;
                 const bool near = isq && abs(c1q - c1p) <= 1;
-                if (__ballot(near) == 0) continue;
-                const int c2lo = wave_min_i(near ? max(c2q - 1, 0) : INT_MAX);
-                const int c2hi = wave_max_i(near ? min(c2q + 1, (int)mask2) : -1);
+                int c2lo, c2hi;
+                block_minmax(wave_min_i(near ? max(c2q - 1, 0) : INT_MAX),
+                             wave_max_i(near ? min(c2q + 1, (int)mask2) : -1), c2lo, c2hi);
+                if (c2lo > c2hi) continue;
                 const uint32_t rk = lbits | ((uint32_t)c1p << cb2);
                 c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c2lo);
                 cend = wave_lower_bound(gkey, c0, pend, (rk | (uint32_t)c2hi) + 1u);
@@ -487,90 +532,103 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl,
         }
         return c0 < cend;
     };
-    // a candidate tile's operands: lane (i, hh) holds candidate c0 + i.  The
-    // loads run two deep: a tile's positions (gval) two tiles ahead of its
-    // use, its operands one tile ahead.
-    struct CandTile {
-        int64_t pc;
-        bool qc;
-        float bj;
-        float4 gc;
-        bf16x8 bH0, bH1, bL0, bL1;
+    // a candidate tile is the positions [tc0, min(tc0 + 32, tend)); the block
+    // loads it with one 16-byte part of one candidate per thread (and the
+    // coordinates of one candidate on each of the first 32 threads)
+    const int ld_c = tid / 8, ld_part = tid % 8;
+    auto load_part = [&](bool have_t, int64_t tc0, int64_t tend, uint4 &op, float4 &cg) {
+        const int64_t pc = tc0 + ld_c;
+        op = have_t && pc < tend ? jop_s[pc * 8 + ld_part] : make_uint4(0, 0, 0, 0);
+        if (tid < kJT) {
+            const int64_t pg = tc0 + tid;
+            cg = have_t && pg < tend ? gp_s[pg] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        }
     };
-    auto load_tile = [&](bool validc, int64_t pc, uint32_t kc) {
-        CandTile t;
-        t.pc = pc;
-        t.gc = validc ? gp[kc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-        const uint4 *o = jop + (int64_t)kc * 8;
-        const uint4 z = make_uint4(0, 0, 0, 0);
-        t.bH0 = as_bf16x8(validc ? o[hh] : z);
-        t.bH1 = as_bf16x8(validc ? o[2 + hh] : z);
-        t.bL0 = as_bf16x8(validc ? o[4 + hh] : z);
-        t.bL1 = as_bf16x8(validc ? o[6 + hh] : z);
-        t.bj = fabsf(t.gc.w);
-        t.qc = validc && signbit(t.gc.w);
-        return t;
+    auto store_part = [&](int buf, const uint4 &op, const float4 &cg) {
+        cop[buf][ld_c][ld_part] = op;
+        if (tid < kJT) cgp[buf][tid] = cg;
     };
-    // tile 0 (current) and tile 1 (next) positions; the iterator then
-    // stands on tile 1
+
     bool have = next_run();
-    const int64_t pc0 = c0 + i;
-    const bool v0 = have && pc0 < cend;
-    const uint32_t kc0 = v0 ? gval[pc0] : 0u;
+    int64_t tc0 = c0, tend = cend;
+    {
+        uint4 op;
+        float4 cg;
+        load_part(have, tc0, tend, op, cg);
+        store_part(0, op, cg);
+    }
+    __syncthreads();
+    // the Gram filter terms of the 16 rows this lane holds, in registers for
+    // the whole walk (rows 8 (r / 4) + 4 hh + r % 4 of the result)
+    float rw[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rw[r] = roww[wv][8 * (r / 4) + 4 * hh + (r % 4)];
+    int cur = 0;
     c0 += kJT;
     bool have1 = have && next_run();
-    int64_t pc1 = c0 + i;
-    bool v1 = have1 && pc1 < cend;
-    uint32_t kc1 = v1 ? gval[pc1] : 0u;
-    CandTile cur = load_tile(v0, pc0, kc0);
-    for (;;) {
-        if (qn > (have ? kQueueHigh : 0)) flush();
-        if (!have) break;
-        // positions of the tile after next, operands of the next tile
-        c0 += kJT;
-        const bool have2 = have1 && next_run();
-        const int64_t pc2 = c0 + i;
-        const bool v2 = have2 && pc2 < cend;
-        const uint32_t kc2 = v2 ? gval[pc2] : 0u;
-        const CandTile nxt = load_tile(v1, pc1, kc1);
+    while (have) {
+        // the next tile's loads, in flight through this tile's work
+        const int64_t nc0 = c0, nend = cend;
+        uint4 op;
+        float4 cg;
+        load_part(have1, nc0, nend, op, cg);
+        // this tile: operands from LDS (lane (i, hh) holds candidate tc0 + i)
+        const bf16x8 bH0 = as_bf16x8(cop[cur][i][hh]), bH1 = as_bf16x8(cop[cur][i][2 + hh]);
+        const bf16x8 bL0 = as_bf16x8(cop[cur][i][4 + hh]), bL1 = as_bf16x8(cop[cur][i][6 + hh]);
+        const float4 gc = cgp[cur][i];
+        const float bj = fabsf(gc.w);
+        const bool qc = gc.w != INFINITY && signbit(gc.w);
         f32x16 acc = {};
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, cur.bH0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, cur.bH1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, cur.bL0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, cur.bL1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, cur.bH0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, cur.bH1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bH0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bH1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bL0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bL1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, bH0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, bH1, acc, 0, 0, 0);
         n_pairs += 16;
         // keep (row, candidate) unless the Gram bound or a coordinate rules it
         // out, or the candidate is a query earlier in the order (its tile
         // takes the pair), or it is the row itself.  Positions relative to
-        // the tile (p0) and to the length (pbeg) fit 32 bits.
-        asm volatile("" ::: "memory");   // read the row table per tile, not once
-        const int pcr = (int)(cur.pc - p0);
-        const uint32_t pcl = (uint32_t)(cur.pc - pbeg), p0l = (uint32_t)(p0 - pbeg);
+        // the query tile (p0) and to the length (pbeg) fit 32 bits.
+        const int64_t pc = tc0 + i;
+        const int pcr = (int)(pc - p0);
+        const uint32_t pcl = (uint32_t)(pc - pbeg), p0l = (uint32_t)(p0 - pbeg);
+        // the Gram test of all 16 rows first: most tiles keep nothing
+        bool anyg = false;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            // the rows of the 32 x 32 result this lane holds: 8 (r / 4) + 4 hh + r % 4
-            const int row = 8 * (r / 4) + 4 * hh + (r % 4);
-            const bool gram = acc[r] >= roww[wv][row] + cur.bj;
-            if (__ballot(gram) == 0) continue;
-            const float4 rc = rowc[wv][row];
-            const bool keep = gram && fabsf(rc.x - cur.gc.x) <= G.rp &&
-                              fabsf(rc.y - cur.gc.y) <= G.rp && fabsf(rc.z - cur.gc.z) <= G.rp &&
-                              pcr != row && !(cur.qc && pcr < row);
-            const uint64_t bal = __ballot(keep);
-            if (bal == 0) continue;
-            if (keep)
-                queue[wv][qn + __popcll(bal & lanemask_lt())] = make_uint2(p0l + (uint32_t)row, pcl);
-            qn += __popcll(bal);
+        for (int r = 0; r < 16; ++r) anyg |= acc[r] >= rw[r] + bj;
+        if (__ballot(anyg)) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                // the rows of the 32 x 32 result this lane holds: 8 (r / 4) + 4 hh + r % 4
+                const int row = 8 * (r / 4) + 4 * hh + (r % 4);
+                const bool gram = acc[r] >= rw[r] + bj;
+                if (__ballot(gram) == 0) continue;
+                const float4 rc = rowc[wv][row];
+                const bool keep = gram && fabsf(rc.x - gc.x) <= G.rp && fabsf(rc.y - gc.y) <= G.rp &&
+                                  fabsf(rc.z - gc.z) <= G.rp && pcr != row && !(qc && pcr < row);
+                const uint64_t bal = __ballot(keep);
+                if (bal == 0) continue;
+                if (keep)
+                    queue[wv][qn + __popcll(bal & lanemask_lt())] =
+                        make_uint2(p0l + (uint32_t)row, pcl);
+                qn += __popcll(bal);
+            }
         }
-        cur = nxt;
+        if (qn > kQueueHigh) flush();
+        // stage the next tile; after the barrier it is the current one
+        store_part(cur ^ 1, op, cg);
+        __syncthreads();
+        cur ^= 1;
         have = have1;
-        have1 = have2;
-        pc1 = pc2;
-        v1 = v2;
-        kc1 = kc2;
+        tc0 = nc0;
+        tend = nend;
+        if (have) {
+            c0 += kJT;
+            have1 = next_run();
+        }
     }
+    if (qn > 0) flush();
     // statistics: one atomic per wavefront
     for (int off = kWave / 2; off > 0; off >>= 1) {
         n_pairs += __shfl_xor(n_pairs, off, kWave);
@@ -606,19 +664,24 @@ void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int c
                        l_lim, i_lim, gkey, gval, qf, gp);
 }
 
+void launch_join_gather(const uint32_t *gval, const uint4 *jop, const float4 *gp, int64_t n,
+                        uint4 *jop_s, float4 *gp_s, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_join_gather, dim3((unsigned)((n * 8 + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, gval, jop, gp, n, jop_s, gp_s);
+}
+
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
-                       const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
-                       const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
-                       int cb3,
-                       double T, hipStream_t s) {
-    if (ntiles <= 0) return;
-    const unsigned nb = (unsigned)((ntiles + kJoinWaves - 1) / kJoinWaves);
+                       const uint32_t *gval, const uint8_t *qf, const uint4 *jop_s,
+                       const float4 *jmeta, const float4 *gp_s, int64_t nblocks, int cb1, int cb2,
+                       int cb3, double T, hipStream_t s) {
+    if (nblocks <= 0) return;
     if (precision == 0)
-        hipLaunchKernelGGL(k_join_tiles<double>, dim3(nb), dim3(kJoinWaves * kWave), 0, s, q, gl,
-                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, cb3, T);
+        hipLaunchKernelGGL(k_join_tiles<double>, dim3((unsigned)nblocks), dim3(kJB * kWave), 0, s,
+                           q, gl, gkey, gval, qf, jop_s, jmeta, gp_s, cb1, cb2, cb3, T);
     else
-        hipLaunchKernelGGL(k_join_tiles<float>, dim3(nb), dim3(kJoinWaves * kWave), 0, s, q, gl,
-                           gkey, gval, qf, jop, jmeta, gp, ntiles, cb1, cb2, cb3, T);
+        hipLaunchKernelGGL(k_join_tiles<float>, dim3((unsigned)nblocks), dim3(kJB * kWave), 0, s,
+                           q, gl, gkey, gval, qf, jop_s, jmeta, gp_s, cb1, cb2, cb3, T);
 }
 
 }  // namespace pmp

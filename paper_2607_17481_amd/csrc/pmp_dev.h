@@ -138,11 +138,12 @@ __device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) 
 }
 
 constexpr int kJoinTile = 32;             // windows per threshold-join tile
+constexpr int kJoinBlock = 4;             // join tiles per block (they share candidate tiles)
 constexpr int kJoinDirs = 3;              // principal directions per length in the join
 
 // Per length, one round of the threshold join (k_join.hip).
 struct GridLen {
-    int64_t tile_base;    // first join tile of this length
+    int64_t blk_base;     // first join block (kJoinBlock tiles) of this length
     double qlo;           // grid origin of both coordinates
     double hinv;          // 1 / cell width of the first coordinate (0: one cell)
     double hinv2;         // 1 / cell width of the second and third coordinates
@@ -488,9 +489,14 @@ void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hi
 void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2, int cb3,
                       int l_lim, int64_t i_lim, uint32_t *gkey, uint32_t *gval, uint8_t *qf,
                       float4 *gp, hipStream_t s);
+// the join operands and coordinates of the first n sorted positions, in
+// sorted order
+void launch_join_gather(const uint32_t *gval, const uint4 *jop, const float4 *gp, int64_t n,
+                        uint4 *jop_s, float4 *gp_s, hipStream_t s);
+// one block of kJoinBlock query tiles per GridLen block, nblocks in all
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
-                       const uint32_t *gval, const uint8_t *qf, const uint4 *jop,
-                       const float4 *jmeta, const float4 *gp, int64_t ntiles, int cb1, int cb2,
+                       const uint32_t *gval, const uint8_t *qf, const uint4 *jop_s,
+                       const float4 *jmeta, const float4 *gp_s, int64_t nblocks, int cb1, int cb2,
                        int cb3, double T, hipStream_t s);
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);

@@ -444,6 +444,8 @@ struct Bufs {
     uint32_t *skey, *sval, *skey2, *sval2, *pcell, *bstart;
     void *sort_tmp;
     uint32_t *jk, *jv, *jk2, *jv2;
+    uint4 *jop_s;              // join operands and coordinates in grid order
+    float4 *gp_s;
     // emit stage: cell -> k map, partner hints, sieve segments and
     // directions, completion seeds
     uint32_t *kmap, *hint, *scnt, *stotal, *sseg, *seeds;
@@ -519,6 +521,8 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, const Opt &o, int k) {
     b.pcell = take<uint32_t>(a, N);
     b.bstart = take<uint32_t>(a, p.nbuckets + 1);
     b.sort_tmp = a.take(sort_temp_bytes(N));
+    b.jop_s = take<uint4>(a, N * 8);
+    b.gp_s = take<float4>(a, N);
     b.jk = take<uint32_t>(a, N);
     b.jv = take<uint32_t>(a, N);
     b.jk2 = take<uint32_t>(a, N);
@@ -1023,10 +1027,12 @@ static int run_pipeline(Run &R, Arena &ar) {
     set_bound();
     if (o.certify && N > 0) {
         std::vector<GridLen> gl(p.L);
-        int64_t ntiles = 0;
+        // join blocks of kJoinBlock tiles of 32 windows, each within one length
+        const int64_t win_per_blk = (int64_t)kJoinTile * kJoinBlock;
+        int64_t nblk = 0;
         for (int l = 0; l < p.L; ++l) {
-            gl[l].tile_base = ntiles;
-            ntiles += (p.len[l].n_index + kJoinTile - 1) / kJoinTile;
+            gl[l].blk_base = nblk;
+            nblk += (p.len[l].n_index + win_per_blk - 1) / win_per_blk;
         }
         // three grid coordinates of cb3d bits each or two of cb bits, as far
         // as every length's radius resolves at that grid's cell width; else
@@ -1093,13 +1099,14 @@ static int run_pipeline(Run &R, Arena &ar) {
             // windows and tiles of the lengths up to the bound (sorted by
             // length first, so they are a prefix)
             const int64_t Nq = p.len[l_lim].kbase + p.len[l_lim].n_index;
-            const int64_t ntq =
-                gl[l_lim].tile_base + (p.len[l_lim].n_index + kJoinTile - 1) / kJoinTile;
+            const int64_t nbq =
+                gl[l_lim].blk_base + (p.len[l_lim].n_index + win_per_blk - 1) / win_per_blk;
             launch_grid_keys(q, b.gl, Nq, cb1, cb2, cb3, l_lim, i_lim, b.jk, b.jv, b.qf, b.gp, s);
             radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, Nq, 0, p.len_bits + cb1 + cb2 + cb3,
                              b.sort_tmp, s);
-            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop, b.jmeta, b.gp, ntq,
-                              cb1, cb2, cb3, Teff, s);
+            launch_join_gather(b.jv, b.jop, b.gp, Nq, b.jop_s, b.gp_s, s);
+            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop_s, b.jmeta, b.gp_s,
+                              nbq, cb1, cb2, cb3, Teff, s);
             HIPCHK(hipGetLastError());
             rc = select_topk(p, b, R.k, s, acc);   // synchronizes: gl may be rewritten next
             if (rc) return rc;

@@ -26,7 +26,7 @@ def _both(pmp, torch, t, lo, hi, excl, prec):
 def test_noalloc_equals_workspace_entry_point_twice(prec):
     import torch
     from paper_2607_17481_amd import pmp
-    big = synth.ecg_like(20_000, 41)
+    big = synth.ecg_like(16_000, 41)
     small = synth.wafer_like(8_000, 42, copies=4)
     for t, lo, hi, excl in ((big, 40, 60, 40), (small, 30, 45, 30)):
         got, st, ref, st_ref = _both(pmp, torch, t, lo, hi, excl, prec)
