@@ -136,11 +136,16 @@ def algorithmic_bytes(n, lengths, st, fs):
         w = n - m + 1
         rd += 12 * (w + -(-w // TILE_W) * (m - 1))   # samples + change-point prefix
     nx = st["indexed_cells"]
-    # the sketch phase, per indexed window: the sketch kernel writes cell,
-    # mu, 1/sigma, P and the record; the keys kernel reads the record back and
-    # writes the join operands (128), their metadata (16), the principal
-    # coordinates (16), the key word (8) and the sort key and value (4 + 4)
-    sketch = rd + nx * (4 + 8 + 8 + 8 + REC * fs) + nx * (REC * fs + 128 + 16 + 16 + 8 + 4 + 4)
+    cells = sum(n - m + 1 for m in lengths)
+    # the sketch kernel: the samples and change-point counts above, the
+    # cell -> indexed position map (4 per cell, kept when lengths between
+    # anchors exist), and per indexed window its cell, mu, 1/sigma, P and
+    # record
+    sketch = rd + (4 * cells if st["anchors"] < len(lengths) else 0) + nx * (4 + 8 + 8 + 8 + REC * fs)
+    # the keys kernel reads the record back and writes the join operands
+    # (128), their metadata (16), the principal coordinates (16), the key
+    # word (8) and the sort key and value (4 + 4)
+    keys = nx * (REC * fs + 128 + 16 + 16 + 8 + 4 + 4)
     # per query: its state; per inspected candidate: slot, P, record; per
     # verified pair: the candidate's moments and the two cell updates (the
     # samples of both windows are read from the series, which stays resident
@@ -150,14 +155,15 @@ def algorithmic_bytes(n, lengths, st, fs):
              + st["pass_verified"] * (16 + 16) + 8 * n)
     join = (nx * 32 + st["join_candidates"] * (REC * fs + 4)
             + st["join_verified"] * (16 + 16) + 8 * n)
-    return {"k_sketch": float(sketch), "k_probe": float(probe), "k_join": float(join)}
+    return {"k_sketch": float(sketch), "k_keys": float(keys), "k_probe": float(probe),
+            "k_join": float(join)}
 
 
-# the source files of each timed phase's kernels: the sketch phase is the
-# sketch, the join's principal directions and the keys; the join phase's
-# dominant kernels are the grid keys and the tile join
-KERNEL_SOURCES = {"k_sketch": ("k_sketch.hip", "k_join.hip"), "k_probe": ("k_probe.hip",),
-                  "k_join": ("k_join.hip", "k_certify.hip")}
+# the source files of each timed kernel: the sketch kernel; the keys (with
+# the join's principal directions before them); the probe; the join phase,
+# whose dominant kernels are the grid keys and the tile join
+KERNEL_SOURCES = {"k_sketch": ("k_sketch.hip",), "k_keys": ("k_sketch.hip", "k_join.hip"),
+                  "k_probe": ("k_probe.hip",), "k_join": ("k_join.hip", "k_certify.hip")}
 
 
 def source_digest(kernel):
@@ -446,13 +452,14 @@ def main():
     value = cells * args.steps / el
     avg = lambda key: float(np.mean([s[key] for s in stats]))  # noqa: E731
 
-    # dominant kernel: the largest of the three main kernels by the library's
+    # dominant kernel: the largest of the four main kernels by the library's
     # own HIP-event brackets (recorded on the stream the kernels run on)
     last = stats[-1]
     lengths = list(range(m_min, m_max + 1, step))
     fs = 8 if args.precision == "fp64" else 4
     alg = algorithmic_bytes(n, lengths, last, fs)
-    kern_ms = {"k_sketch": avg("ms_sketch"), "k_probe": avg("ms_probe"), "k_join": avg("ms_join")}
+    kern_ms = {"k_sketch": avg("ms_sketch"), "k_keys": avg("ms_keys"), "k_probe": avg("ms_probe"),
+               "k_join": avg("ms_join")}
     dom = max(kern_ms, key=kern_ms.get)
     achieved = alg[dom] / (kern_ms[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom, args.workload, args.precision)

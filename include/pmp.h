@@ -128,7 +128,8 @@ typedef struct {
     double   ms_onepass;        /* moments + sketch + buckets + probe         */
     double   ms_certify;        /* selection + threshold join + exact rows
                                    (after the emit stage, ms_complete)        */
-    double   ms_sketch;
+    double   ms_sketch;         /* the sketch kernel (FP64 sliding DFT, or the
+                                   basis tables + MFMA projection)           */
     double   ms_sort;
     double   ms_probe;
     double   ms_join;
@@ -143,6 +144,8 @@ typedef struct {
     int32_t  anchors;           /* anchor lengths probed                      */
     double   ms_sieve;          /* the hot-class sieve (part of ms_complete)  */
     double   ms_hints;          /* the hints (part of ms_complete)            */
+    double   ms_keys;           /* principal directions + keys (after the
+                                   sketch kernel, within the sketch phase)   */
 } pmp_stats;
 
 /* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),
@@ -241,6 +244,96 @@ int pmp_wait(pmp_server *srv, uint64_t req_id, pmp_motif *out, int32_t *n_out,
 
 /* Waits for every admitted request and frees the server. */
 void pmp_server_destroy(pmp_server *srv);
+
+/* ----------------------------------------------------------- streaming */
+
+/* A stream session (Sec. 3.1, 3.5, Algorithm 1): samples arrive in order and
+ * are processed in batches of `batch` <= exclusion consecutive samples.  At
+ * every anchor length (every anchor_stride-th length of m_min..m_max by
+ * m_step, and the last, Sec. 3.3) each sample completes the window that ends
+ * at it; a batch's windows get their features and SimHash keys, search the
+ * earlier windows of their length in the anchor's directory (exact-prefix
+ * bucket and Hamming-1 probes, budget gamma * budget, Parseval prune, exact
+ * FP64 distances) and lower the upper profile of both ends.  Windows of one
+ * batch never search each other (they are all within the exclusion zone).
+ * The series and all state stay on the GPU; updates at sample tau use only
+ * samples 0..tau.  The profile is deterministic for a given input, batch
+ * size and options (Prop. 5): how the samples are split over append calls
+ * does not change it, since batches are cut at multiples of `batch` from the
+ * first sample (pmp_stream_flush cuts one early).
+ * Sessions are not thread-safe; one session uses one device.
+ *
+ * Memory: about 330 bytes per (sample, anchor length) of `capacity` on the
+ * device, 4 bytes per sample on the host; an exact query adds the
+ * workspace pmp_run_device needs for the samples held. */
+typedef struct pmp_stream pmp_stream;
+
+typedef struct {
+    uint64_t appended;      /* samples appended                              */
+    uint64_t processed;     /* samples whose batch has run                   */
+    uint64_t batches;       /* batches run                                   */
+    uint64_t windows;       /* non-constant anchor windows completed         */
+    uint64_t candidates;    /* candidates inspected (Parseval bound)         */
+    uint64_t verified;      /* exact distances computed                      */
+    uint64_t updates;       /* candidate-end improvements merged             */
+    uint64_t dropped;       /* improvements lost to a full buffer (0: the
+                               buffer holds R per window by construction)   */
+    int32_t  anchors;       /* anchor lengths                                */
+    int32_t  K;             /* spectral width (the option, 16 if 0: a stream
+                               has no series to calibrate on in advance)    */
+    int32_t  batch;         /* samples per batch                             */
+    int32_t  reserved;
+    double   ms_ingest;     /* device time of the batches so far             */
+    uint64_t device_bytes;  /* reserved (0)                                  */
+} pmp_stream_stats;
+
+/* Opens a session on `device` for up to `capacity` samples.  batch 0 means
+ * batch = exclusion.  Options as pmp_open_ex (NULL = defaults); only the
+ * FP64 form (precision 0) is accepted.  *out receives the session.
+ * Errors: PMP_EINVAL unless 3 <= m_min <= m_max <= min(capacity, 2048),
+ * k >= 1, exclusion >= 1, budget >= 1, 1 <= batch <= exclusion and the
+ * anchor cells (capacity times anchor lengths) stay below 2^31;
+ * PMP_EDEVICE for a bad device; PMP_ENOMEM when the device memory is not
+ * there. */
+int pmp_stream_create(int device, int64_t capacity, int32_t m_min, int32_t m_max,
+                      int32_t k, int32_t exclusion, int32_t budget, int32_t batch,
+                      const pmp_options *opt, pmp_stream **out);
+
+/* Appends `count` samples (host memory, copied before return) and runs
+ * every batch they complete; a remainder shorter than a batch waits for the
+ * next append.  Returns after the batches ran.  PMP_EINVAL for a non-finite
+ * sample (nothing is appended) or past the capacity. */
+int pmp_stream_append(pmp_stream *s, const double *samples, int64_t count);
+
+/* Runs the pending remainder as a batch of its own. */
+int pmp_stream_flush(pmp_stream *s);
+
+/* Top-k pan-motifs of the upper profile at the anchor lengths over the
+ * samples processed so far (the one-pass result, Sec. 2 top-k rule):
+ * each reported distance is the exact distance of a valid pair, which the
+ * true profile can only undercut.  out: capacity k. */
+int pmp_stream_topk(pmp_stream *s, pmp_motif *out, int32_t *n_out);
+
+/* Exact top-k pan-motifs over all lengths of the samples appended so far:
+ * the certified request path (pmp_run_device) on the resident series, with
+ * the session's parameters; stats as pmp_run_device (NULL = none). */
+int pmp_stream_exact(pmp_stream *s, pmp_motif *out, int32_t *n_out,
+                     pmp_stats *stats);
+
+/* The upper profile of anchor `anchor` (0-based, ascending lengths): *W
+ * receives its windows so far (processed samples - m + 1, or 0); P (FP64,
+ * +inf where no pair was evaluated or the window is constant) and I (the
+ * neighbour, -1 where none) receive W values each when not NULL. */
+int pmp_stream_profile(pmp_stream *s, int32_t anchor, double *P, int64_t *I,
+                       int64_t *W);
+
+/* Counters; lengths (when not NULL) receives up to `capacity` anchor
+ * lengths. */
+int pmp_stream_info(pmp_stream *s, pmp_stream_stats *st, int32_t *lengths,
+                    int32_t capacity);
+
+/* Waits for the session's work and frees it (NULL: nothing). */
+void pmp_stream_destroy(pmp_stream *s);
 
 /* Text of the last error on this thread ("" if none). */
 const char *pmp_last_error(void);

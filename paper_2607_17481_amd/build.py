@@ -22,8 +22,8 @@ LIB = os.path.join(PKG, "libpmp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["k_scan.hip", "k_sketch.hip", "k_probe.hip", "k_complete.hip", "k_certify.hip",
-           "k_join.hip",
-           "pmp_host.hip",
+           "k_join.hip", "k_stream.hip",
+           "pmp_host.hip", "pmp_stream.hip",
            "pmp_server.cpp"]
 
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-Wall",

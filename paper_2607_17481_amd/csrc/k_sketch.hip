@@ -222,35 +222,12 @@ __device__ __forceinline__ void tile_positions_and_moments(
     for (int v = 0; v < kBlock / kWave; ++v) nix += (int)wsum[v];
 
     // ---- moments (two-pass, population; Sec. 3.2), one thread per
-    // non-constant window; four partial sums keep the LDS loads independent
+    // non-constant window
     for (int xi = tid; xi < nix; xi += kBlock) {
         const int w = widx[xi];
         const int32_t kk = kpos[w];
-        const double *x = st + w;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int r = 0;
-        for (; r + 4 <= m; r += 4) {
-            a0 += x[r];
-            a1 += x[r + 1];
-            a2 += x[r + 2];
-            a3 += x[r + 3];
-        }
-        for (; r < m; ++r) a0 += x[r];
-        const double mu = ((a0 + a1) + (a2 + a3)) / (double)m;
-        a0 = a1 = a2 = a3 = 0.0;
-        for (r = 0; r + 4 <= m; r += 4) {
-            const double c0 = x[r] - mu, c1 = x[r + 1] - mu;
-            const double c2 = x[r + 2] - mu, c3 = x[r + 3] - mu;
-            a0 = fma(c0, c0, a0);
-            a1 = fma(c1, c1, a1);
-            a2 = fma(c2, c2, a2);
-            a3 = fma(c3, c3, a3);
-        }
-        for (; r < m; ++r) {
-            const double c0 = x[r] - mu;
-            a0 = fma(c0, c0, a0);
-        }
-        const double sg = sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
+        double mu;
+        const double sg = window_moments(st + w, m, mu);
         double is = 1.0 / sg;
         if (!(sg > 0.0) || !isfinite(sg) || !(is > 0.0) || !isfinite(is)) {
             // samples differ but sigma underflows or overflows: outside the
@@ -552,13 +529,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double ecomp = sqrt((double)L.kprime) * per * (double)m * (1.0 + 1e-6);
     const double eabs = sqrt(2.0 * L.kprime) * (double)m * 0x1.0p-122;
     float emax = 0.0f;
-    for (int blk = wv; blk < kTileW / kMBlk; blk += kBlock / kWave) {
-        const int w0 = blk * kMBlk;
-        if (w0 >= nw) break;
-        const int32_t kw = i < nw - w0 ? kpos[w0 + i] : -1;
-        if (__ballot(kw >= 0) == 0) continue;
-        const double mu = kw >= 0 ? smu[w0 + i] : 0.0;
-        const double *x = st + w0 + i + 8 * hh;      // window i, this lane's half of each chunk
+    // blocks of 32 non-constant windows, from the tile's compacted list
+    // (lanes past its end project window 0 and store nothing)
+    int nix = 0;
+    for (int v = 0; v < kBlock / kWave; ++v) nix += (int)wsum[v];
+    for (int blk = wv; blk * kMBlk < nix; blk += kBlock / kWave) {
+        const int x0 = blk * kMBlk;
+        const bool has = x0 + i < nix;
+        const int wi = has ? (int)widx[x0 + i] : 0;
+        const double mu = has ? smu[wi] : 0.0;
+        const double *x = st + wi + 8 * hh;          // window i, this lane's half of each chunk
 
         double sum[16];
 #pragma unroll
@@ -619,10 +599,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // records: lane i holds feature i of 16 windows (rows 8 (v/4) + 4 hh
         // + v % 4); the 16 norms are summed over the 32 feature lanes together
         float fv[16], n2[16];
+        int wr[16];                                   // the window of each row, or -1
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int w = w0 + 8 * (v / 4) + 4 * hh + (v % 4);
-            const double is = w < nw && kpos[w] >= 0 ? sis[w] : 0.0;
+            const int xr = x0 + 8 * (v / 4) + 4 * hh + (v % 4);
+            wr[v] = xr < nix ? (int)widx[xr] : -1;
+            const double is = wr[v] >= 0 ? sis[wr[v]] : 0.0;
             fv[v] = (float)(sum[v] * is);
             n2[v] = fv[v] * fv[v];
         }
@@ -632,9 +614,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             for (int v = 0; v < 16; ++v) n2[v] += __shfl_xor(n2[v], off, kMBlk);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int w = w0 + 8 * (v / 4) + 4 * hh + (v % 4);
-            const int32_t kk = w < nw ? kpos[w] : -1;
-            if (kk >= 0) {
+            const int w = wr[v];
+            if (w >= 0) {
+                const int32_t kk = kpos[w];
                 const double is = sis[w];
                 float *rec = (float *)q.F + (int64_t)kk * kRec;
                 // the FP32 sum of 30 squares is within 32 u32 of exact

@@ -308,6 +308,37 @@ __device__ __forceinline__ int find_len_k_wave(const LenInfo *len, int L, int64_
     return lo;
 }
 
+// Canonical moments of one window x[0..m) (Sec. 3.2: population, two
+// passes): returns sigma and sets mu.  Four partial sums in a fixed order
+// keep the loads independent; every caller gets the same bits for the same
+// samples, which the distances below depend on.
+__device__ __forceinline__ double window_moments(const double *x, int m, double &mu) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int r = 0;
+    for (; r + 4 <= m; r += 4) {
+        a0 += x[r];
+        a1 += x[r + 1];
+        a2 += x[r + 2];
+        a3 += x[r + 3];
+    }
+    for (; r < m; ++r) a0 += x[r];
+    mu = ((a0 + a1) + (a2 + a3)) / (double)m;
+    a0 = a1 = a2 = a3 = 0.0;
+    for (r = 0; r + 4 <= m; r += 4) {
+        const double c0 = x[r] - mu, c1 = x[r + 1] - mu;
+        const double c2 = x[r + 2] - mu, c3 = x[r + 3] - mu;
+        a0 = fma(c0, c0, a0);
+        a1 = fma(c1, c1, a1);
+        a2 = fma(c2, c2, a2);
+        a3 = fma(c3, c3, a3);
+    }
+    for (; r < m; ++r) {
+        const double c0 = x[r] - mu;
+        a0 = fma(c0, c0, a0);
+    }
+    return sqrt(((a0 + a1) + (a2 + a3)) / (double)m);
+}
+
 // Certified lower bound on d_m(q, c) from two stored feature records: the
 // Parseval bound (Lemma 2) of the true features is at least
 //   sqrt(2/m) (||F~q - F~c|| - e_q - e_c),
@@ -417,6 +448,70 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, A qa, const doub
     }
 }
 
+// ------------------------------------------------------------- stream
+
+// One anchor length of a stream session, as the kernels of one batch see it
+// (Sec. 3.1, 3.5, Algorithm 1).  Cells of the anchor are its window starts
+// q at cbase + q.  The directory is the anchor's indexed windows in
+// arrival order, cut into sorted runs: run r holds the indexed positions
+// [runs[r], runs[r + 1]), sorted by (SimHash key, start).
+constexpr int kStreamMaxRuns = 48;
+struct SAnchor {
+    int32_t m, kprime;
+    int64_t cbase;        // first cell
+    int64_t bbase;        // offset of the basis table (2 K' rows of m doubles)
+    int32_t nidx;         // indexed windows before this batch
+    int32_t nnew;         // indexed windows this batch completes
+    int32_t j0;           // first entry of the batch list that is this anchor's
+    int32_t depth;        // directory depth d (Prop. 4)
+    int32_t probes;       // Hamming-1 probes h
+    int32_t nruns;
+    uint32_t runs[kStreamMaxRuns + 1];
+};
+
+// A candidate endpoint's improvement, merged after the batch's searches.
+struct SUpdate {
+    uint32_t cell;
+    int32_t j;            // the query start that reached it
+    uint64_t d;           // FP64 bits of the distance
+};
+
+// One merge of the newest runs of one anchor into a single run.
+struct SMerge {
+    int64_t cbase;
+    int64_t first;        // first thread of this merge in the launch
+    int32_t nruns;        // runs merged
+    int32_t pad_;
+    uint32_t runs[kStreamMaxRuns + 1];
+};
+
+// Kernel arguments of a stream batch.
+struct StreamDev {
+    const double *t;      // resident series
+    double *F;            // [cells][kRec] records
+    double *mu, *isig;    // [cells]
+    uint64_t *P;          // [cells] upper profile (FP64 bits; +inf: none)
+    int32_t *I;           // [cells] its neighbour (-1: none)
+    int32_t *Icand;       // [cells] merge scratch
+    uint32_t *perm, *skey;   // [cells] directory runs (start, key) by position
+    uint32_t *ptmp, *ktmp;   // [cells] merge scratch
+    const double *basis;
+    const float *gproj;   // [anchor][kMaxBits][30] SimHash projections
+    const SAnchor *anc;
+    const int32_t *la, *lq;  // batch list: anchor, start
+    int32_t nlist;
+    int32_t B;            // signature bits
+    int32_t R;            // budget per query (gamma alpha)
+    int32_t excl;
+    uint32_t *bkey;       // [list] SimHash key
+    float *bmarg;         // [list][kMaxBits] projection margins
+    SUpdate *upd;
+    uint32_t *nupd;
+    uint32_t updcap;
+    unsigned long long *counters;   // kStreamCounters
+};
+enum { CS_CAND = 0, CS_VER, CS_UPD, CS_DROP, kStreamCounters };
+
 // --------------------------------------------------- host-side launchers
 // (k_scan.hip)
 size_t scan_temp_bytes(int64_t n);
@@ -500,6 +595,15 @@ void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uin
                        int cb3, double T, hipStream_t s);
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
+void launch_stream_basis(const SAnchor *anc, int na, int64_t elems, double *basis,
+                         hipStream_t s);
+void launch_stream_windows(const StreamDev &S, int max_m, hipStream_t s);
+void launch_stream_probe(const StreamDev &S, hipStream_t s);
+void launch_stream_apply(const StreamDev &S, hipStream_t s);
+void launch_stream_newruns(const StreamDev &S, int na, hipStream_t s);
+void launch_stream_merge(const StreamDev &S, const SMerge *mg, int nmerge, int64_t nthreads,
+                         hipStream_t s);
+void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,

@@ -11,6 +11,7 @@
 #include "pmp_dev.h"
 #include "pmp.h"
 #include "pmp_stages.h"
+#include "pmp_host.h"
 
 #include <algorithm>
 #include <cmath>
@@ -28,7 +29,7 @@ namespace pmp {
 
 static thread_local std::string g_err;
 
-static int fail(int code, const char *fmt, ...) {
+int fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -38,37 +39,9 @@ static int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIPCHK(x)                                                                        \
-    do {                                                                                 \
-        hipError_t e_ = (x);                                                             \
-        if (e_ != hipSuccess)                                                            \
-            return fail(PMP_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_));       \
-    } while (0)
+void clear_error() { g_err.clear(); }
 
-// ------------------------------------------------------------ options
-
-struct Opt {
-    int m_step = 1;
-    int precision = PMP_PREC_FP64;
-    int K = 0;
-    uint64_t seed = 0x5eed2607u;
-    int certify = 1;
-    int B = 24;
-    int gamma = 8;
-    int d0 = 12;
-    int probe_cap = 8;
-    // anchor lengths and emit-time completion (Sec. 3.3, 3.6).  The stride is
-    // the paper's maximum-performance one (App. E; its default is 2) and the
-    // sieve is off (its default width is 8): both measured faster here, and
-    // neither changes the certified result
-    int stride = 6;
-    int sieve_w = 0;
-    int compl_rounds = 8;
-    int compl_dm = 6;
-    int compl_dp = 4;
-};
-
-static int read_options(const pmp_options *o, Opt &out) {
+int read_options(const pmp_options *o, Opt &out) {
     Opt d;
     if (o) {
         if (o->size != sizeof(pmp_options))
@@ -126,14 +99,13 @@ static double gauss(uint64_t seed, int m, int l, int c) {
     return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586476925286766559 * u2);
 }
 
-constexpr int kFD = 2 * (kMaxK - 1);   // 30 feature reals
 
 // The SimHash projections of one length (kMaxBits x 30, a pure function of
 // the seed and m) into out, from a table kept across requests: a request
 // over 51 lengths needs 36,720 Gaussian draws, about 1.7 ms of host time
 // while the GPU would wait.  The table is bounded (cleared past 8192
 // lengths) and shared by the server's threads.
-static void projections(uint64_t seed, int m, float *out) {
+void projections(uint64_t seed, int m, float *out) {
     static std::mutex mu;
     static std::map<std::pair<uint64_t, int>, std::vector<float>> table;
     std::lock_guard<std::mutex> lock(mu);
@@ -148,7 +120,7 @@ static void projections(uint64_t seed, int m, float *out) {
     std::memcpy(out, it->second.data(), it->second.size() * sizeof(float));
 }
 
-static int kprime_of(int K, int m) {
+int kprime_of(int K, int m) {
     int half = (m + 1) / 2 - 1;
     int kp = std::min(K - 1, half);
     return kp < 0 ? 0 : kp;
@@ -459,9 +431,8 @@ struct Bufs {
     uint32_t *less_k, *less_cell, *eq_k, *eq_cell;
 };
 
-static int64_t need_select(int k, int m_max) { return (int64_t)k * (m_max + 1); }
-constexpr size_t kSelHead = 256;          // SelState, padded
-static size_t select_block_bytes(int64_t need) { return kSelHead + (size_t)need * 24; }
+int64_t need_select(int k, int m_max) { return (int64_t)k * (m_max + 1); }
+size_t select_block_bytes(int64_t need) { return kSelHead + (size_t)need * 24; }
 
 static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
     b.len = take<LenInfo>(a, p.L);
@@ -628,7 +599,7 @@ static int select_topk(const Plan &p, Bufs &b, int k, hipStream_t s, std::vector
 // Phase times from HIP events on the request's stream.  Off (no events
 // created at all) for callers that must not allocate.
 struct Timer {
-    hipEvent_t ev[11] = {};
+    hipEvent_t ev[12] = {};
     bool ok = false;
     explicit Timer(bool on) {
         if (!on) return;
@@ -958,6 +929,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         launch_sketch_mfma(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, b.bbase, b.bh, b.bm,
                            b.bl, s);
     }
+    tm.mark(11, s);
     // the join's principal directions (GPU), used by the keys kernel
     if (o.certify && N > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
     launch_keys(o.precision, q, p.nkblocks, s);
@@ -1252,7 +1224,8 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->ms_complete = tm.ms(5, 8);
         st->ms_sieve = tm.ms(5, 9);
         st->ms_hints = tm.ms(9, 10);
-        st->ms_sketch = tm.ms(1, 2);
+        st->ms_sketch = tm.ms(1, 11);
+        st->ms_keys = tm.ms(11, 2);
         st->ms_sort = tm.ms(2, 3);
         st->ms_probe = tm.ms(4, 5);
         st->ms_join = tm.ms(8, 6);

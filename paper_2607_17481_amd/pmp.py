@@ -50,7 +50,8 @@ class Stats(C.Structure):
                 ("sieve_verified", C.c_uint64), ("hint_verified", C.c_uint64),
                 ("complete_verified", C.c_uint64), ("ms_complete", C.c_double),
                 ("complete_rounds", C.c_int32), ("anchors", C.c_int32),
-                ("ms_sieve", C.c_double), ("ms_hints", C.c_double)]
+                ("ms_sieve", C.c_double), ("ms_hints", C.c_double),
+                ("ms_keys", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("size", "reserved")}
@@ -67,6 +68,14 @@ class Debug(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("submit_s", C.c_double), ("start_s", C.c_double), ("end_s", C.c_double),
                 ("cells", C.c_uint64), ("workspace_bytes", C.c_uint64)]
+
+
+class StreamStats(C.Structure):
+    _fields_ = [("appended", C.c_uint64), ("processed", C.c_uint64), ("batches", C.c_uint64),
+                ("windows", C.c_uint64), ("candidates", C.c_uint64), ("verified", C.c_uint64),
+                ("updates", C.c_uint64), ("dropped", C.c_uint64), ("anchors", C.c_int32),
+                ("K", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32),
+                ("ms_ingest", C.c_double), ("device_bytes", C.c_uint64)]
 
 
 @dataclass(frozen=True)
@@ -118,6 +127,15 @@ def lib():
             L.pmp_wait.argtypes = [vp, u64, vp, vp, vp]
             L.pmp_server_destroy.argtypes = [vp]
             L.pmp_server_destroy.restype = None
+        L.pmp_stream_create.argtypes = [C.c_int, i64, i32, i32, i32, i32, i32, i32, vp, vp]
+        L.pmp_stream_append.argtypes = [vp, vp, i64]
+        L.pmp_stream_flush.argtypes = [vp]
+        L.pmp_stream_topk.argtypes = [vp, vp, vp]
+        L.pmp_stream_exact.argtypes = [vp, vp, vp, vp]
+        L.pmp_stream_profile.argtypes = [vp, i32, vp, vp, vp]
+        L.pmp_stream_info.argtypes = [vp, vp, vp, i32]
+        L.pmp_stream_destroy.argtypes = [vp]
+        L.pmp_stream_destroy.restype = None
         _lib = L
     return _lib
 
@@ -281,6 +299,69 @@ class Server:
     def close(self):
         if self.h:
             lib().pmp_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Stream:
+    """pmp_stream_*: a stream session (see include/pmp.h)."""
+
+    def __init__(self, capacity: int, m_min: int, m_max: int, k: int, exclusion: int,
+                 budget: int = 16, batch: int = 0, opts: Options | None = None, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().pmp_stream_create(device, capacity, m_min, m_max, k, exclusion, budget, batch,
+                                       C.byref(opts) if opts is not None else None, C.byref(h)))
+        self.h = h
+        self.k = k
+
+    def append(self, samples):
+        t = np.ascontiguousarray(samples, dtype=np.float64)
+        _check(lib().pmp_stream_append(self.h, t.ctypes.data_as(C.c_void_p), len(t)))
+
+    def flush(self):
+        _check(lib().pmp_stream_flush(self.h))
+
+    def topk(self):
+        out = (MotifC * self.k)()
+        n_out = C.c_int32(0)
+        _check(lib().pmp_stream_topk(self.h, out, C.byref(n_out)))
+        return _motifs(out, n_out.value)
+
+    def exact(self, stats: bool = False):
+        out = (MotifC * self.k)()
+        n_out = C.c_int32(0)
+        st = Stats()
+        st.size = C.sizeof(Stats)
+        _check(lib().pmp_stream_exact(self.h, out, C.byref(n_out), C.byref(st)))
+        res = _motifs(out, n_out.value)
+        return (res, st.as_dict()) if stats else res
+
+    def info(self):
+        st = StreamStats()
+        lengths = (C.c_int32 * 64)()
+        _check(lib().pmp_stream_info(self.h, C.byref(st), lengths, 64))
+        d = {f: getattr(st, f) for f, _ in StreamStats._fields_}
+        d["lengths"] = [int(lengths[a]) for a in range(min(st.anchors, 64))]
+        return d
+
+    def profile(self, anchor: int):
+        """(P, I) of anchor `anchor` over the windows processed so far."""
+        W = C.c_int64(0)
+        _check(lib().pmp_stream_profile(self.h, anchor, None, None, C.byref(W)))
+        P = np.empty(W.value, dtype=np.float64)
+        I = np.empty(W.value, dtype=np.int64)
+        _check(lib().pmp_stream_profile(self.h, anchor, P.ctypes.data_as(C.c_void_p),
+                                        I.ctypes.data_as(C.c_void_p), C.byref(W)))
+        return P, I
+
+    def close(self):
+        if self.h:
+            lib().pmp_stream_destroy(self.h)
             self.h = None
 
     def __enter__(self):

@@ -87,7 +87,8 @@ def test_struct_layouts_match_the_headers(tmp_path):
     import subprocess
     from paper_2607_17481_amd import pmp
     pairs = [("pmp_motif", pmp.MotifC), ("pmp_options", pmp.Options), ("pmp_stats", pmp.Stats),
-             ("pmp_timing", pmp.Timing), ("pmp_debug", pmp.Debug)]
+             ("pmp_timing", pmp.Timing), ("pmp_debug", pmp.Debug),
+             ("pmp_stream_stats", pmp.StreamStats)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pmp_stages.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} (sizeof) %zu\\n", sizeof({cname}));')
@@ -107,3 +108,26 @@ def test_struct_layouts_match_the_headers(tmp_path):
         assert got[(cname, "(sizeof)")] == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_stream_argument_checks():
+    """pmp_stream_create rejects bad arguments before it touches a device."""
+    from paper_2607_17481_amd import pmp
+    L = pmp.lib()
+    h = C.c_void_p()
+    cases = [dict(batch=65),                       # batch > exclusion
+             dict(capacity=50),                    # capacity < m_max
+             dict(m_min=2),                        # m_min < 3
+             dict(k=0), dict(budget=0), dict(exclusion=0),
+             dict(opts=pmp.options(precision=1)),  # FP64 form only
+             dict(opts=pmp.options(anchor_stride=0))]
+    for kw in cases:
+        a = dict(capacity=1000, m_min=32, m_max=82, k=20, exclusion=64, budget=16, batch=0,
+                 opts=None)
+        a.update(kw)
+        rc = L.pmp_stream_create(0, a["capacity"], a["m_min"], a["m_max"], a["k"], a["exclusion"],
+                                 a["budget"], a["batch"],
+                                 C.byref(a["opts"]) if a["opts"] is not None else None, C.byref(h))
+        assert rc == pmp.PMP_EINVAL, kw
+        assert not h.value
+        assert L.pmp_last_error()
