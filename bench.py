@@ -271,6 +271,42 @@ def serving_bench(cfg):
     return out
 
 
+STREAM_DEFAULT = {"n": 1_000_000, "chunk": 65_536}
+
+
+def streaming_bench(workload, n=STREAM_DEFAULT["n"], chunk=STREAM_DEFAULT["chunk"]):
+    """A stream session over the first n samples of the workload's series
+    (batches of beta = exclusion samples, appended chunk samples at a time):
+    ingest throughput, device time per batch, then the exact query on the
+    resident series, checked against the request path on the same samples."""
+    import torch
+    from paper_2607_17481_amd import pmp
+    gen, _, seed, m_min, m_max, step, excl, k = WORKLOADS[workload]
+    t = make_series(workload)[:n]
+    with pmp.Stream(len(t), m_min, m_max, k, excl, 16, 0, pmp.options(m_step=step)) as s:
+        t0 = time.perf_counter()
+        for x in range(0, len(t), chunk):
+            s.append(t[x:x + chunk])
+        s.flush()
+        el = time.perf_counter() - t0
+        info = s.info()
+        anchor_cells = sum(max(0, len(t) - m + 1) for m in info["lengths"])
+        t1 = time.perf_counter()
+        ex, st = s.exact(stats=True)
+        ex_ms = (time.perf_counter() - t1) * 1e3
+    td = torch.from_numpy(t).cuda()
+    ref, _ = pmp.run_device(td, m_min, m_max, k, excl, 16, pmp.options(m_step=step),
+                            pmp.Workspace("cuda:0"))
+    return {"n": len(t), "batch": info["batch"], "anchors": info["lengths"],
+            "samples_per_s": len(t) / el, "anchor_cells_per_s": anchor_cells / el,
+            "batches": info["batches"], "us_per_batch": el * 1e6 / max(1, info["batches"]),
+            "device_ms": info["ms_ingest"], "candidates": info["candidates"],
+            "verified": info["verified"], "updates": info["updates"],
+            "exact_query_ms": ex_ms,
+            "exact_same_as_request_path": [(r.i, r.j, r.m) for r in ex] == [(r.i, r.j, r.m)
+                                                                          for r in ref]}
+
+
 SERVING_SWEEP = {"requests": 120, "n_lo": 10_000, "n_hi": 2_000_000, "slots": 4,
                  "hbm_budget_gb": 192, "loads": (0.5, 0.8, 1.0)}
 
@@ -390,6 +426,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-stream", action="store_true", help="skip the stream measurement")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the copy kernel that scales the HBM counters")
@@ -534,6 +571,8 @@ def main():
         line["serving"] = serving_bench(SERVING_DEFAULT)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.workload)
+    if not args.no_stream:
+        line["streaming"] = streaming_bench(args.workload)
     print(json.dumps(line), flush=True)
 
 
