@@ -142,10 +142,9 @@ def algorithmic_bytes(n, lengths, st, fs):
     # anchors exist), and per indexed window its cell, mu, 1/sigma, P and
     # record
     sketch = rd + (4 * cells if st["anchors"] < len(lengths) else 0) + nx * (4 + 8 + 8 + 8 + REC * fs)
-    # the keys kernel reads the record back and writes the join operands
-    # (128), their metadata (16), the principal coordinates (16), the key
-    # word (8) and the sort key and value (4 + 4)
-    keys = nx * (REC * fs + 128 + 16 + 16 + 8 + 4 + 4)
+    # the keys kernel reads the record back and writes the key word (8) and
+    # the sort key and value (4 + 4)
+    keys = nx * (REC * fs + 8 + 4 + 4)
     # per query: its state; per inspected candidate: slot, P, record; per
     # verified pair: the candidate's moments and the two cell updates (the
     # samples of both windows are read from the series, which stays resident
@@ -153,7 +152,10 @@ def algorithmic_bytes(n, lengths, st, fs):
     probe = (nx * (REC * fs + 4 + 4 + 8 + 8 + 8 + 8 + 4)
              + st["pass_candidates"] * (REC * fs + 4 + 4 + 8)
              + st["pass_verified"] * (16 + 16) + 8 * n)
-    join = (nx * 32 + st["join_candidates"] * (REC * fs + 4)
+    # the join: its queried windows' operands (record read; 128 + 16 + 16
+    # written), grid keys and sort, then per kept pair ...
+    nj = st.get("join_windows", nx)
+    join = (nj * (REC * fs + 128 + 16 + 16) + nx * 32 + st["join_candidates"] * (REC * fs + 4)
             + st["join_verified"] * (16 + 16) + 8 * n)
     return {"k_sketch": float(sketch), "k_keys": float(keys), "k_probe": float(probe),
             "k_join": float(join)}
@@ -162,8 +164,9 @@ def algorithmic_bytes(n, lengths, st, fs):
 # the source files of each timed kernel: the sketch kernel; the keys (with
 # the join's principal directions before them); the probe; the join phase,
 # whose dominant kernels are the grid keys and the tile join
-KERNEL_SOURCES = {"k_sketch": ("k_sketch.hip",), "k_keys": ("k_sketch.hip", "k_join.hip"),
-                  "k_probe": ("k_probe.hip",), "k_join": ("k_join.hip", "k_certify.hip")}
+KERNEL_SOURCES = {"k_sketch": ("k_sketch.hip",), "k_keys": ("k_sketch.hip",),
+                  "k_probe": ("k_probe.hip",),
+                  "k_join": ("k_join.hip", "k_certify.hip", "k_sketch.hip")}
 
 
 def source_digest(kernel):

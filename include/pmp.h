@@ -144,8 +144,10 @@ typedef struct {
     int32_t  anchors;           /* anchor lengths probed                      */
     double   ms_sieve;          /* the hot-class sieve (part of ms_complete)  */
     double   ms_hints;          /* the hints (part of ms_complete)            */
-    double   ms_keys;           /* principal directions + keys (after the
-                                   sketch kernel, within the sketch phase)   */
+    double   ms_keys;           /* SimHash keys (after the sketch kernel,
+                                   within the sketch phase)                  */
+    uint64_t join_windows;      /* windows given join operands (the lengths
+                                   up to the key bound of the last round)    */
 } pmp_stats;
 
 /* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),

@@ -102,8 +102,6 @@ constexpr int kStageLd = 31;                  // doubles per staged row (odd: th
 struct SketchSmem {
     int32_t kpos[kTileW];                     // indexed position, -1: constant window
     uint16_t widx[kTileW];                    // the tile's non-constant windows, in order
-    uint8_t rows[kSegW / kSlidesC][kRowsC];   // indexed staging rows of each chunk
-    int32_t nrows[kSegW / kSlidesC];
     float ymax[kSegs];                        // largest |t - c| of each segment
     uint32_t wsum[kBlock / kWave];
     int emax;
@@ -159,6 +157,26 @@ __device__ __forceinline__ void sketch_record(const Req &q, int m, int kprime,
         *(float4 *)(rec + 28) = make_float4(f[28], f[29], e, (float)nrm);
     }
     emax = fmaxf(emax, e);
+}
+
+// A tile's samples into LDS: st[r] = t[i0 + r] for r < nvalid, 0 up to
+// ntotal.  Every load of a thread is issued before the first LDS write, so a
+// tile waits for memory once, not once per 256 samples.
+__device__ __forceinline__ void load_tile_samples(const double *__restrict__ t, int64_t i0,
+                                                  int nvalid, int ntotal, double *st) {
+    constexpr int kLd = (kTileW + kMaxM + 64) / kBlock + 1;   // covers every tile and halo
+    const int tid = threadIdx.x;
+    double v[kLd];
+#pragma unroll
+    for (int x = 0; x < kLd; ++x) {
+        const int r = tid + x * kBlock;
+        v[x] = r < nvalid ? t[i0 + r] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < kLd; ++x) {
+        const int r = tid + x * kBlock;
+        if (r < ntotal) st[r] = v[x];
+    }
 }
 
 // Shared first steps of a sketch tile (samples already in LDS): the
@@ -252,15 +270,15 @@ __device__ __forceinline__ void tile_positions_and_moments(
 
 // One block per tile of 1024 consecutive windows of one length.
 //  1. samples into LDS; compacted position of every non-constant window;
-//     two-pass moments of those windows (one thread per window); the list
-//     of non-constant windows of each chunk (below);
+//     two-pass moments of those windows (one thread per window);
 //  2. thread (segment g = tid / 16, bin b = tid % 16) owns bin k = b + 1 of
 //     the 64 windows of segment g: it computes the bin directly at the
 //     segment start (four independent phasor chains, so the sum is not one
 //     long dependent chain) and slides it 63 times, in FP64;
-//  3. every 8 slides the 128 new windows' raw bins are staged in LDS, and the
-//     non-constant ones among them, packed onto consecutive threads, get
-//     their records one per thread (sketch_record).
+//  3. every 8 slides the new windows' raw bins are staged in LDS, and each
+//     wavefront gives the non-constant ones of its four segments their
+//     records, one per lane (sketch_record), with no barrier of the block:
+//     the wavefronts of a tile run their segments independently.
 // Keys and join records follow in k_keys, one thread per non-constant
 // window with every lane busy.
 template <typename FT>
@@ -283,32 +301,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
     double(*stage)[kStageLd] = (double(*)[kStageLd])(dyn + st_len);   // kRowsC rows
 
     if (tid == 0) sm.emax = 0;
-    for (int r = tid; r < nw + m - 1; r += kBlock) st[r] = q.t[i0 + r];
+    load_tile_samples(q.t, i0, nw + m - 1, nw + m - 1, st);
     // feature slots beyond K' stay zero in every staging row
     for (int x = tid; x < kRowsC * (kFD - 2 * kp); x += kBlock)
         stage[x / (kFD - 2 * kp)][2 * kp + x % (kFD - 2 * kp)] = 0.0;
 
     tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, sm.kpos, sm.widx, sm.wsum);
-    // ---- per chunk, the staging rows that hold a non-constant window;
-    // wavefront wv lists its share of the chunks (row = segment * kSlidesC +
-    // slide), kWave rows at a time
-    constexpr int kChunksW = kSegW / kSlidesC / (kBlock / kWave);
-#pragma unroll
-    for (int h = 0; h < kChunksW; ++h) {
-        const int chunk = kChunksW * wv + h;
-        int base = 0;
-#pragma unroll
-        for (int half = 0; half < kRowsC / kWave; ++half) {
-            const int row = half * kWave + lane;
-            const int s = (row / kSlidesC) * kSegW + chunk * kSlidesC + (row % kSlidesC);
-            const bool ix = s < nw && sm.kpos[s] >= 0;
-            const uint64_t bal = __ballot(ix);
-            if (ix) sm.rows[chunk][base + __popcll(bal & lanemask_lt())] = (uint8_t)row;
-            base += __popcll(bal);
-        }
-        if (lane == 0) sm.nrows[chunk] = base;
-    }
-
     // ---- sliding DFT in FP64: thread (segment g, bin b)
     const int b = tid & 15;
     const int g = tid >> 4;
@@ -369,7 +367,25 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         xi = (ai[0] + ai[1]) + (ai[2] + ai[3]);
     }
 
+    // Each wavefront owns segments 4 wv .. 4 wv + 3, i.e. staging rows
+    // 32 wv .. 32 wv + 31, and finishes their windows itself: from here on it
+    // synchronizes with no other wavefront.
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // the record lanes' 1/sigma of every chunk, loaded together
+    double isr[kSegW / kSlidesC];
+#pragma unroll
+    for (int chunk = 0; chunk < kSegW / kSlidesC; ++chunk) {
+        const int row = 4 * kSlidesC * wv + lane;
+        const int s = (row / kSlidesC) * kSegW + chunk * kSlidesC + (row % kSlidesC);
+        const int32_t kk = lane < 4 * kSlidesC && s < nw ? sm.kpos[s] : -1;
+        isr[chunk] = kk >= 0 ? q.isig[kk] : 0.0;
+    }
     float emax = 0.0f;
+#pragma unroll
     for (int chunk = 0; chunk < kSegW / kSlidesC; ++chunk) {
         // ---- 8 slides of every (segment, bin), raw bins into the staging rows
         if (own) {
@@ -389,17 +405,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
                 rw[2 * b + 1] = xi;
             }
         }
-        __syncthreads();
-
-        // ---- the chunk's non-constant windows, one per thread
-        for (int x = tid; x < sm.nrows[chunk]; x += kBlock) {
-            const int row = sm.rows[chunk][x];
+        wave_sync();
+        // ---- the chunk's non-constant windows of this wavefront's segments,
+        // one per lane
+        if (lane < 4 * kSlidesC) {
+            const int row = 4 * kSlidesC * wv + lane;
             const int sg = row / kSlidesC;
             const int s = sg * kSegW + chunk * kSlidesC + (row % kSlidesC);
-            const int32_t kk = sm.kpos[s];
-            sketch_record<FT>(q, m, kp, stage[row], q.isig[kk], sm.ymax[sg], kk, emax);
+            const int32_t kk = s < nw ? sm.kpos[s] : -1;
+            if (kk >= 0) sketch_record<FT>(q, m, kp, stage[row], isr[chunk], sm.ymax[sg], kk, emax);
         }
-        __syncthreads();
+        wave_sync();
     }
     // largest e_i of the tile: one LDS atomic per wavefront
     int eb = __float_as_int(emax);
@@ -498,7 +514,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     double *st = dyn;                              // samples, 1024 + m - 1 (+ zero pad)
 
     if (tid == 0) emax_s = 0;
-    for (int r = tid; r < nw + mp + kMBlk; r += kBlock) st[r] = r < nw + m - 1 ? q.t[i0 + r] : 0.0;
+    load_tile_samples(q.t, i0, nw + m - 1, nw + mp + kMBlk, st);
     tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, widx, wsum, smu, sis);
 
     const uint4 *Bh = (const uint4 *)(bh + bbase[l]);
@@ -642,55 +658,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (tid == 0 && emax_s) atomicMax((int *)&q.emax[l], emax_s);
 }
 
-// SimHash keys, probe order, bucket sort key and join operands of every
-// non-constant window, from its stored record.  Blocks are laid out per
-// length (blk_base), so the length's projections sit in LDS for all threads.
+// SimHash keys, probe order and bucket sort key of every non-constant
+// window, from its stored record.  Blocks are laid out per length
+// (blk_base), so the length's projections sit in LDS for all threads.
 namespace {
-struct KeysSmem {
-    // SimHash projections (bit x feature), bf16 hi, lo; rows of 40 (80 bytes,
-    // an odd multiple of 16) so that the lanes' 16-byte reads of different
-    // rows fall in different banks
-    uint16_t gh[32][40], gl[32][40];
-    float dots[kBlock / kWave][2][32][33];    // each wavefront's 64 x 32 projections
-    double u[kJoinDirs][32];                  // the join's principal directions
-};
 
-}  // namespace
-
-template <typename FT, bool kBf16Keys>
-__global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict__ gproj) {
-    __shared__ KeysSmem sm;
-    int l;
-    {
-        int lo = 0, hi = q.L - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (q.len[mid].blk_base <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
-        }
-        l = lo;
-    }
-    const LenInfo L = q.len[l];
-    const int tid = threadIdx.x;
-    for (int x = tid; x < 32 * 32; x += kBlock) {
-        const int bt = x / 32, c = x % 32;
-        const float gv = bt < q.B && c < kFD ? gproj[((int64_t)l * q.B + bt) * kFD + c] : 0.0f;
-        const uint32_t h = bf16_bits(gv);
-        sm.gh[bt][c] = (uint16_t)h;
-        sm.gl[bt][c] = (uint16_t)bf16_bits(gv - __uint_as_float(h << 16));
-    }
-    if (q.udir)
-        for (int x = tid; x < kJoinDirs * 32; x += kBlock)
-            sm.u[x / 32][x % 32] = q.udir[(int64_t)l * kJoinDirs * 32 + x];
-    __syncthreads();
-    const int64_t j = ((int64_t)blockIdx.x - L.blk_base) * kBlock + tid;
-    // every lane takes part in the wavefront's matrix products; lanes past
-    // the length's last window carry zeros and write nothing
-    const bool valid = j < L.n_index;
-    const int64_t kk = L.kbase + (valid ? j : 0);
-
+// The FP32 copy f of a window's stored features (zeros when !valid), with
+// the record's error bound and norm.
+template <typename FT>
+__device__ __forceinline__ void load_fcopy(const Req &q, int64_t kk, bool valid, float f[kFD],
+                                           float &erec, float &nrec) {
     const FT *rec = (const FT *)q.F + kk * kRec;
-    float f[kFD];
-    float erec = 0.0f, nrec = 0.0f;
+    erec = nrec = 0.0f;
 #pragma unroll
     for (int c = 0; c < kFD; ++c) f[c] = 0.0f;
     if (valid && sizeof(FT) == 8) {
@@ -718,11 +697,13 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
         erec = v.z;
         nrec = v.w;
     }
+}
 
-    // ---- the FP32 copy as bf16 pairs: G = hi + lo, hi = bf16(f),
-    // lo = bf16(f - hi); each component of G is within 2^-17 of f (relative)
-    uint32_t hw[16], lw[16];
-    double n2 = 0.0;
+// The FP32 copy as bf16 pairs: G = hi + lo, hi = bf16(f), lo = bf16(f - hi);
+// each component of G is within 2^-17 of f (relative).  n2 = |G|^2 (FP64).
+__device__ __forceinline__ void bf16_pairs(const float f[kFD], uint32_t hw[16], uint32_t lw[16],
+                                           double &n2) {
+    n2 = 0.0;
 #pragma unroll
     for (int w = 0; w < 16; ++w) {
         uint32_t hp = 0, lp = 0;
@@ -741,45 +722,97 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
         hw[w] = hp;
         lw[w] = lp;
     }
+}
 
-    // ---- principal coordinates of the FP32 copy (FP64 dots), for the
-    // join's grid (f is not needed past this point)
-    float pc0 = 0.0f, pc1 = 0.0f, pc2 = 0.0f;
-    if (q.udir) {
-        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < kFD; ++c) {
-            p0 = fma(sm.u[0][c], (double)f[c], p0);
-            p1 = fma(sm.u[1][c], (double)f[c], p1);
-            p2 = fma(sm.u[2][c], (double)f[c], p2);
-        }
-        pc0 = (float)p0;
-        pc1 = (float)p1;
-        pc2 = (float)p2;
-    }
+}  // namespace
 
-    // ---- join operands (the bf16 pairs above; written first, so that only
-    // the pairs stay live through the matrix products): f is within u32 |F~|
-    // of the stored record F~, itself within e of F; so
-    // e' = e + (u32 + 2^-17) |F~| bounds |G - F|
-    if (valid) {
-        uint4 *jo = q.jop + kk * 8;
+// The threshold join's operands of the indexed windows [k0, k1), one thread
+// each, written only when a join runs and only for the windows it queries
+// (lengths up to the key bound): the bf16 pairs G, their metadata and the
+// principal coordinates of the FP32 copy (FP64 dots) that place the grid.
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_join_ops(Req q, int64_t k0, int64_t k1) {
+    const int64_t kk = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (kk >= k1) return;
+    const int64_t k_first = k0 + (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int l = find_len_k_wave(q.len, q.L, k_first, kk);
+    float f[kFD];
+    float erec, nrec;
+    load_fcopy<FT>(q, kk, true, f, erec, nrec);
+    uint32_t hw[16], lw[16];
+    double n2;
+    bf16_pairs(f, hw, lw, n2);
+    const double *u = q.udir + (int64_t)l * kJoinDirs * 32;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
 #pragma unroll
-        for (int part = 0; part < 4; ++part) {
-            jo[part] = make_uint4(hw[4 * part], hw[4 * part + 1], hw[4 * part + 2], hw[4 * part + 3]);
-            jo[4 + part] = make_uint4(lw[4 * part], lw[4 * part + 1], lw[4 * part + 2], lw[4 * part + 3]);
-        }
-        // w: the join's candidate Gram term 0.5 |G|^2, rounded down (its sign
-        // bit is set per certify round by the grid keys)
-        if (q.udir)
-            q.gp[kk] = make_float4(pc0, pc1, pc2,
-                                   (float)(0.5 * (double)(float)n2 * (1.0 - 0x1.0p-23)));
-        const double ep =
-            ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
-        q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),
-                                  (float)((double)nrec * (1.0 + 0x1.0p-16)) * (1.0f + 2.4e-7f),
-                                  0.0f);
+    for (int c = 0; c < kFD; ++c) {
+        p0 = fma(u[c], (double)f[c], p0);
+        p1 = fma(u[32 + c], (double)f[c], p1);
+        p2 = fma(u[64 + c], (double)f[c], p2);
     }
+    // f is within u32 |F~| of the stored record F~, itself within e of F;
+    // so e' = e + (u32 + 2^-17) |F~| bounds |G - F|
+    uint4 *jo = q.jop + kk * 8;
+#pragma unroll
+    for (int part = 0; part < 4; ++part) {
+        jo[part] = make_uint4(hw[4 * part], hw[4 * part + 1], hw[4 * part + 2], hw[4 * part + 3]);
+        jo[4 + part] = make_uint4(lw[4 * part], lw[4 * part + 1], lw[4 * part + 2], lw[4 * part + 3]);
+    }
+    // w: the join's candidate Gram term 0.5 |G|^2, rounded down (its sign
+    // bit is set per certify round by the grid keys)
+    q.gp[kk] = make_float4((float)p0, (float)p1, (float)p2,
+                           (float)(0.5 * (double)(float)n2 * (1.0 - 0x1.0p-23)));
+    const double ep =
+        ((double)erec + (5.9604644775390625e-08 + 0x1.0p-17) * (double)nrec) * (1.0 + 1e-6);
+    q.jmeta[kk] = make_float4((float)n2, (float)ep * (1.0f + 2.4e-7f),
+                              (float)((double)nrec * (1.0 + 0x1.0p-16)) * (1.0f + 2.4e-7f), 0.0f);
+}
+
+namespace {
+struct KeysSmem {
+    // SimHash projections (bit x feature), bf16 hi, lo; rows of 40 (80 bytes,
+    // an odd multiple of 16) so that the lanes' 16-byte reads of different
+    // rows fall in different banks
+    uint16_t gh[32][40], gl[32][40];
+    float dots[kBlock / kWave][2][32][33];    // each wavefront's 64 x 32 projections
+};
+
+}  // namespace
+
+template <typename FT, bool kBf16Keys>
+__global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict__ gproj) {
+    __shared__ KeysSmem sm;
+    int l;
+    {
+        int lo = 0, hi = q.L - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.len[mid].blk_base <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+        }
+        l = lo;
+    }
+    const LenInfo L = q.len[l];
+    const int tid = threadIdx.x;
+    for (int x = tid; x < 32 * 32; x += kBlock) {
+        const int bt = x / 32, c = x % 32;
+        const float gv = bt < q.B && c < kFD ? gproj[((int64_t)l * q.B + bt) * kFD + c] : 0.0f;
+        const uint32_t h = bf16_bits(gv);
+        sm.gh[bt][c] = (uint16_t)h;
+        sm.gl[bt][c] = (uint16_t)bf16_bits(gv - __uint_as_float(h << 16));
+    }
+    __syncthreads();
+    const int64_t j = ((int64_t)blockIdx.x - L.blk_base) * kBlock + tid;
+    // every lane takes part in the wavefront's matrix products; lanes past
+    // the length's last window carry zeros and write nothing
+    const bool valid = j < L.n_index;
+    const int64_t kk = L.kbase + (valid ? j : 0);
+
+    float f[kFD];
+    float erec = 0.0f, nrec = 0.0f;
+    load_fcopy<FT>(q, kk, valid, f, erec, nrec);
+    uint32_t hw[16], lw[16];
+    double n2;
+    bf16_pairs(f, hw, lw, n2);
 
     // ---- SimHash projections <g_b, G> of the wavefront's 64 windows on the
     // matrix cores: two blocks of 32 windows x 32 bits (B used) over 32
@@ -938,6 +971,15 @@ void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const ui
     (void)precision;
     hipLaunchKernelGGL(k_sketch_mfma, dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
                        tile_off, bbase, bh, bm, bl);
+}
+
+void launch_join_ops(int precision, const Req &q, int64_t k0, int64_t k1, hipStream_t s) {
+    if (k1 <= k0) return;
+    const unsigned g = (unsigned)((k1 - k0 + kBlock - 1) / kBlock);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_join_ops<double>, dim3(g), dim3(kBlock), 0, s, q, k0, k1);
+    else
+        hipLaunchKernelGGL(k_join_ops<float>, dim3(g), dim3(kBlock), 0, s, q, k0, k1);
 }
 
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s) {

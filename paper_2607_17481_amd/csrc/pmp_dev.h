@@ -533,6 +533,7 @@ void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t nt
 void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                    int64_t ntiles, int max_m, hipStream_t s);
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s);
+void launch_join_ops(int precision, const Req &q, int64_t k0, int64_t k1, hipStream_t s);
 int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base);
 void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, uint16_t *bm,
                   uint16_t *bl, int max_m, hipStream_t s);

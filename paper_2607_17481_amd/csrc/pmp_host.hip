@@ -930,8 +930,6 @@ static int run_pipeline(Run &R, Arena &ar) {
                            b.bl, s);
     }
     tm.mark(11, s);
-    // the join's principal directions (GPU), used by the keys kernel
-    if (o.certify && N > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
     launch_keys(o.precision, q, p.nkblocks, s);
     tm.mark(2, s);
     if (radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits,
@@ -997,6 +995,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         }
     };
     set_bound();
+    int64_t nq_ops = 0;                      // windows whose join operands exist
     if (o.certify && N > 0) {
         std::vector<GridLen> gl(p.L);
         // join blocks of kJoinBlock tiles of 32 windows, each within one length
@@ -1073,6 +1072,11 @@ static int run_pipeline(Run &R, Arena &ar) {
             const int64_t Nq = p.len[l_lim].kbase + p.len[l_lim].n_index;
             const int64_t nbq =
                 gl[l_lim].blk_base + (p.len[l_lim].n_index + win_per_blk - 1) / win_per_blk;
+            // the join's operands, for the windows this round queries that
+            // have none yet (the principal directions first, once)
+            if (nq_ops == 0 && Nq > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
+            launch_join_ops(o.precision, q, nq_ops, Nq, s);
+            nq_ops = std::max(nq_ops, Nq);
             launch_grid_keys(q, b.gl, Nq, cb1, cb2, cb3, l_lim, i_lim, b.jk, b.jv, b.qf, b.gp, s);
             radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, Nq, 0, p.len_bits + cb1 + cb2 + cb3,
                              b.sort_tmp, s);
@@ -1210,6 +1214,7 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->join_candidates = ctr[C_JOIN_CAND];
         st->join_verified = ctr[C_JOIN_VER];
         st->join_pairs = ctr[C_JOIN_PAIRS];
+        st->join_windows = (uint64_t)nq_ops;
         st->sieve_verified = ctr[C_SIEVE_VER];
         st->hint_verified = ctr[C_HINT_VER];
         st->complete_verified = ctr[C_COMPL_VER];
