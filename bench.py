@@ -161,9 +161,9 @@ def algorithmic_bytes(n, lengths, st, fs):
             "k_join": float(join)}
 
 
-# the source files of each timed kernel: the sketch kernel; the keys (with
-# the join's principal directions before them); the probe; the join phase,
-# whose dominant kernels are the grid keys and the tile join
+# the source files of each timed kernel: the sketch kernel; the keys; the
+# probe; the join phase (the join's operands and principal directions, the
+# grid keys and the tile join)
 KERNEL_SOURCES = {"k_sketch": ("k_sketch.hip",), "k_keys": ("k_sketch.hip",),
                   "k_probe": ("k_probe.hip",),
                   "k_join": ("k_join.hip", "k_certify.hip", "k_sketch.hip")}
