@@ -40,6 +40,7 @@ WORKLOADS = {
 }
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
 
 
 def make_series(name):
@@ -145,11 +146,13 @@ def algorithmic_bytes(n, lengths, st, fs):
     # the keys kernel reads the record back and writes the key word (8) and
     # the sort key and value (4 + 4)
     keys = nx * (REC * fs + 8 + 4 + 4)
-    # per query: its state; per inspected candidate: slot, P, record; per
+    # per query (an indexed window of an anchor length): its state; per
+    # inspected candidate: slot, P, record; per
     # verified pair: the candidate's moments and the two cell updates (the
     # samples of both windows are read from the series, which stays resident
     # in the caches: 8 n bytes in all)
-    probe = (nx * (REC * fs + 4 + 4 + 8 + 8 + 8 + 8 + 4)
+    nq = st.get("probe_queries", nx)
+    probe = (nq * (REC * fs + 4 + 4 + 8 + 8 + 8 + 8 + 4)
              + st["pass_candidates"] * (REC * fs + 4 + 4 + 8)
              + st["pass_verified"] * (16 + 16) + 8 * n)
     # the join: its queried windows' operands (record read; 128 + 16 + 16
@@ -215,11 +218,12 @@ SERVING_DEFAULT = {"requests": 96, "n_lo": 10_000, "n_hi": 500_000, "slots": 4,
                    "hbm_budget_gb": 96}
 
 
-def serving_run(precision, reqs, series, rate, slots, budget, progress=False):
+def serving_run(precision, reqs, series, rate, slots, budget, progress=False, detail=False):
     """Open loop: each request is submitted at its Poisson arrival time; the
     server admits it when a slot and HBM budget are free.  Latency is the
     library's clock from submission to results in host memory.  With
-    `progress`, every tenth completed request is reported on stderr."""
+    `progress`, every tenth completed request is reported on stderr; with
+    `detail`, every request's latency and service time are returned too."""
     import threading
     from paper_2607_17481_amd import pmp
     opts = pmp.options(precision=precision)
@@ -252,8 +256,15 @@ def serving_run(precision, reqs, series, rate, slots, budget, progress=False):
     lat = np.array([tm["end_s"] - tm["submit_s"] for tm in results])
     span = max(tm["end_s"] for tm in results) - min(tm["submit_s"] for tm in results)
     cells = sum(r.cells for r in reqs)
-    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "req_per_s": len(reqs) / span, "samples_lengths_per_s": cells / span}
+    out = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "req_per_s": len(reqs) / span, "samples_lengths_per_s": cells / span}
+    if detail:
+        out["per_request"] = [
+            {"index": r.index, "kind": r.kind, "n": r.n, "lengths": r.m_max - r.m_min + 1,
+             "cells": r.cells, "latency_ms": (tm["end_s"] - tm["submit_s"]) * 1e3,
+             "service_ms": (tm["end_s"] - tm["start_s"]) * 1e3}
+            for r, tm in zip(reqs, results)]
+    return out
 
 
 def serving_bench(cfg):
@@ -272,6 +283,53 @@ def serving_bench(cfg):
     for name, prec in (("fp64", 0), ("fp32", 1)):
         out[name] = serving_run(prec, reqs, series, rate, cfg["slots"], budget)
     return out
+
+
+# the serving configuration at its full shape: 2000 Poisson requests, series
+# lengths log-uniform on [1e4, 2e6], offered at 0.8 x the plain FP64
+# capacity (measured closed loop on the first capacity_requests)
+SERVING_FULL = {"requests": 2000, "n_lo": 10_000, "n_hi": 2_000_000, "slots": 4,
+                "hbm_budget_gb": 192, "load": 0.8, "capacity_requests": 300}
+
+
+def _series_of(r):
+    return r.series()
+
+
+def serving_full(form, first, count, capacity):
+    """One part of the full serving measurement: without `capacity`, the
+    closed-loop FP64 capacity over the first capacity_requests; otherwise
+    requests [first, first + count) of the 2000, offered open loop at load x
+    capacity with their arrival times shifted to start at 0, in `form`, with
+    every request's latency.  The parts are separate runs (each starts with
+    an empty server); the per-request lines are combined afterwards."""
+    import dataclasses
+    import multiprocessing as mp
+    cfg = SERVING_FULL
+    reqs = synth.serving_requests(cfg["requests"], 1.0, cfg["n_lo"], cfg["n_hi"])
+    budget = cfg["hbm_budget_gb"] << 30
+    if capacity is None:
+        seg = reqs[:cfg["capacity_requests"]]
+    else:
+        seg = reqs[first:first + count]
+        base = seg[0].arrival_s
+        seg = [dataclasses.replace(r, arrival_s=r.arrival_s - base) for r in seg]
+    # the series are generated before anything touches the GPU
+    with mp.get_context("fork").Pool(16) as pool:
+        series = pool.map(_series_of, seg, chunksize=4)
+    print(f"{len(seg)} series ready", file=sys.stderr, flush=True)
+    if capacity is None:
+        r = serving_run(0, seg, series, 0.0, cfg["slots"], budget, True)
+        print(json.dumps({"metric": "serving capacity (closed loop)", "form": "fp64",
+                          "requests": len(seg), "capacity_req_per_s": r["req_per_s"],
+                          "samples_lengths_per_s": r["samples_lengths_per_s"]}), flush=True)
+        return
+    r = serving_run(PREC[form], seg, series, cfg["load"] * capacity, cfg["slots"], budget, True,
+                    detail=True)
+    r.update({"metric": "serving latency (open loop)", "form": form, "first": first,
+              "count": len(seg), "capacity_req_per_s": capacity, "load": cfg["load"],
+              "offered_req_per_s": cfg["load"] * capacity})
+    print(json.dumps(r), flush=True)
 
 
 STREAM_DEFAULT = {"n": 1_000_000, "chunk": 65_536}
@@ -430,6 +488,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-stream", action="store_true", help="skip the stream measurement")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="one part of the 2000-request serving measurement (see serving_full)")
+    ap.add_argument("--first", type=int, default=0)
+    ap.add_argument("--count", type=int, default=1000)
+    ap.add_argument("--capacity", type=float, default=None)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the copy kernel that scales the HBM counters")
@@ -452,6 +515,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.serving_full:
+        serving_full(args.precision, args.first, args.count, args.capacity)
         return
     if args.serving_sweep:
         cfg = dict(SERVING_SWEEP, requests=args.sweep_requests,
@@ -501,8 +567,22 @@ def main():
     kern_ms = {"k_sketch": avg("ms_sketch"), "k_keys": avg("ms_keys"), "k_probe": avg("ms_probe"),
                "k_join": avg("ms_join")}
     dom = max(kern_ms, key=kern_ms.get)
-    achieved = alg[dom] / (kern_ms[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom, args.workload, args.precision)
+    if dom == "k_join":
+        # the threshold join's ceiling is its filter on the matrix cores: per
+        # filtered pair three split-bf16 products of the 32-wide feature
+        # vectors (hi.hi, hi.lo, lo.hi), 3 x 32 x 2 = 192 flop
+        flops = float(last["join_pairs"]) * 192.0
+        achieved = flops / (kern_ms[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": traffic,
+                "algorithmic_flops": flops, "algorithmic_bytes": alg[dom],
+                "kernel_ms": kern_ms[dom]}
+    else:
+        achieved = alg[dom] / (kern_ms[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes": alg[dom], "kernel_ms": kern_ms[dom]}
     line = {
         "metric": "samples*lengths/sec to exact top-20 pan-motifs",
         "value": value,
@@ -529,10 +609,7 @@ def main():
                                       "complete_verified", "complete_rounds", "hot_buckets")},
         "certify_rounds": last["certify_rounds"],
         "K": last["K"],
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes": alg[dom],
-                     "kernel_ms": kern_ms[dom]},
+        "roofline": roof,
         "kernel_ms": kern_ms,
         "indexed_cells": last["indexed_cells"],
         "pass_candidates": last["pass_candidates"],
@@ -540,6 +617,8 @@ def main():
         "join_candidates": last["join_candidates"],
         "join_verified": last["join_verified"],
         "join_pairs": last["join_pairs"],
+        "join_windows": last["join_windows"],
+        "probe_queries": last["probe_queries"],
         "top1": [res[0].i, res[0].j, res[0].m, res[0].dist] if res else None,
     }
     if not args.no_forms:

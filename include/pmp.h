@@ -148,6 +148,8 @@ typedef struct {
                                    within the sketch phase)                  */
     uint64_t join_windows;      /* windows given join operands (the lengths
                                    up to the key bound of the last round)    */
+    uint64_t probe_queries;     /* indexed windows of the anchor lengths (the
+                                   probe's queries)                          */
 } pmp_stats;
 
 /* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),

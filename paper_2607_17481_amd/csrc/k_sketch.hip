@@ -375,18 +375,19 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    // the record lanes' 1/sigma of every chunk, loaded together
-    double isr[kSegW / kSlidesC];
-#pragma unroll
-    for (int chunk = 0; chunk < kSegW / kSlidesC; ++chunk) {
+    // the record lane's 1/sigma for a chunk, loaded one chunk ahead so that
+    // the slides hide its latency
+    auto isig_of = [&](int chunk) -> double {
         const int row = 4 * kSlidesC * wv + lane;
         const int s = (row / kSlidesC) * kSegW + chunk * kSlidesC + (row % kSlidesC);
         const int32_t kk = lane < 4 * kSlidesC && s < nw ? sm.kpos[s] : -1;
-        isr[chunk] = kk >= 0 ? q.isig[kk] : 0.0;
-    }
+        return kk >= 0 ? q.isig[kk] : 0.0;
+    };
+    double is_next = isig_of(0);
     float emax = 0.0f;
-#pragma unroll
     for (int chunk = 0; chunk < kSegW / kSlidesC; ++chunk) {
+        const double is_cur = is_next;
+        if (chunk + 1 < kSegW / kSlidesC) is_next = isig_of(chunk + 1);
         // ---- 8 slides of every (segment, bin), raw bins into the staging rows
         if (own) {
             const int u_end = min(kSlidesC, segn - chunk * kSlidesC);
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
             const int sg = row / kSlidesC;
             const int s = sg * kSegW + chunk * kSlidesC + (row % kSlidesC);
             const int32_t kk = s < nw ? sm.kpos[s] : -1;
-            if (kk >= 0) sketch_record<FT>(q, m, kp, stage[row], isr[chunk], sm.ymax[sg], kk, emax);
+            if (kk >= 0) sketch_record<FT>(q, m, kp, stage[row], is_cur, sm.ymax[sg], kk, emax);
         }
         wave_sync();
     }

@@ -1215,6 +1215,9 @@ static int run_pipeline(Run &R, Arena &ar) {
         st->join_verified = ctr[C_JOIN_VER];
         st->join_pairs = ctr[C_JOIN_PAIRS];
         st->join_windows = (uint64_t)nq_ops;
+        st->probe_queries = 0;
+        for (int l = 0; l < p.L; ++l)
+            if (p.len[l].anchor) st->probe_queries += (uint64_t)p.len[l].n_index;
         st->sieve_verified = ctr[C_SIEVE_VER];
         st->hint_verified = ctr[C_HINT_VER];
         st->complete_verified = ctr[C_COMPL_VER];

@@ -51,7 +51,8 @@ class Stats(C.Structure):
                 ("complete_verified", C.c_uint64), ("ms_complete", C.c_double),
                 ("complete_rounds", C.c_int32), ("anchors", C.c_int32),
                 ("ms_sieve", C.c_double), ("ms_hints", C.c_double),
-                ("ms_keys", C.c_double), ("join_windows", C.c_uint64)]
+                ("ms_keys", C.c_double), ("join_windows", C.c_uint64),
+                ("probe_queries", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("size", "reserved")}
