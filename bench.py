@@ -401,7 +401,7 @@ PARAM_SWEEP = {"alpha": (4, 8, 16, 32, 64), "K": (4, 8, 12, 16), "maxperf": (4, 
 # the paper's App. E study of the anchor stride, the sieve width, the local
 # completion's round cap and radii; each entry: label, options
 EMIT_SWEEP = (
-    [(f"stride {s}", dict(anchor_stride=s)) for s in (1, 2, 3, 4, 6, 8)]
+    [(f"stride {s}", dict(anchor_stride=s)) for s in (1, 2, 3, 4, 6, 8, 12, 16)]
     + [(f"sieve w {w}", dict(sieve_width=w)) for w in (0, 2, 8, 32)]
     + [(f"rounds {r}", dict(complete_rounds=r)) for r in (0, 1, 8)]
     + [(f"radii {dm},{dp}", dict(complete_dm=dm, complete_dp=dp)) for dm, dp in ((2, 1), (12, 8))]

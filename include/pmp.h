@@ -288,7 +288,8 @@ typedef struct {
     int32_t  batch;         /* samples per batch                             */
     int32_t  reserved;
     double   ms_ingest;     /* device time of the batches so far             */
-    uint64_t device_bytes;  /* reserved (0)                                  */
+    uint64_t device_bytes;  /* device memory the session holds, with the
+                               exact query's workspace once grown           */
 } pmp_stream_stats;
 
 /* Opens a session on `device` for up to `capacity` samples.  batch 0 means

@@ -71,6 +71,7 @@ struct pmp_stream {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double ms_ingest = 0.0;
     std::vector<void *> allocs;
+    uint64_t dev_bytes = 0;               // device memory held (without the exact query's)
 };
 
 namespace {
@@ -84,6 +85,7 @@ int dalloc(pmp_stream *s, T **p, int64_t count) {
         return fail(PMP_ENOMEM, "stream: hipMalloc of %zu bytes failed", bytes);
     }
     s->allocs.push_back(v);
+    s->dev_bytes += bytes;
     *p = (T *)v;
     return PMP_OK;
 }
@@ -189,7 +191,8 @@ int run_batch(pmp_stream *s, int64_t end) {
         const int last = (int)rb.size() - 2;             // the new run
         int first = last;
         while (first > 0 && rb[first] - rb[first - 1] <= rb.back() - rb[first]) --first;
-        while ((int)rb.size() - 1 - (last - first) > kStreamMaxRuns) --first;   // never reached
+        // (the counter keeps about log2 N runs; this bound is not reached in practice)
+        while (first > 0 && (int)rb.size() - 1 - (last - first) > kStreamMaxRuns) --first;
         if (first < last) {
             SMerge M{};
             M.cbase = A.cbase;
@@ -590,7 +593,7 @@ int pmp_stream_info(pmp_stream *s, pmp_stream_stats *st, int32_t *lengths, int32
     st->K = s->K;
     st->batch = s->beta;
     st->ms_ingest = s->ms_ingest;
-    st->device_bytes = 0;
+    st->device_bytes = s->dev_bytes + s->ws_bytes;
     if (lengths)
         for (int a = 0; a < (int)s->anc.size() && a < capacity; ++a) lengths[a] = s->anc[a].m;
     return PMP_OK;
