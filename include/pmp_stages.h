@@ -48,6 +48,12 @@ typedef struct {
        prefix lies within it, Sec. 3.6), so this forces the rounds after the
        first, which real data reaches only rarely.  Other values: EINVAL. */
     double   t_start_scale;
+    /* in: 0 = off.  A positive value caps the threshold join's buffer of
+       kept pairs (between its tiles and its exact stage) at that many pairs,
+       so that the tiles verify the pairs past the cap themselves, as they do
+       when a round keeps more pairs than the buffer holds.  The result is
+       the same.  Negative values: EINVAL. */
+    int64_t  join_pair_cap;
 } pmp_debug;
 
 int pmp_run_device_debug(const double *d_series, int64_t n, int32_t m_min,

@@ -24,7 +24,11 @@
 //    that bound exceeds R^2;
 //  * exact: kept pairs pass the exclusion test, the certified Parseval bound
 //    from the stored records (<= T and below one of the two cells) and are
-//    verified with the canonical FP64 distance, lowering both cells.
+//    verified with the canonical FP64 distance, lowering both cells.  The
+//    tiles hand their kept pairs to a buffer, and the exact stage runs as a
+//    kernel of its own (k_join_verify) after each chunk of tiles: the tiles
+//    walk in step as a block, so an exact stage inside them would hold the
+//    block's other wavefronts at the next barrier.
 //
 // Every unordered pair is examined once: a pair whose other end is itself a
 // query and comes earlier in the order is left to that end's tile (both ends
@@ -37,7 +41,7 @@ namespace pmp {
 namespace {
 
 constexpr int kJT = kJoinTile;                // queries / candidates per tile
-constexpr int kQueueHigh = 256;               // kept pairs buffered before the exact stage runs
+constexpr int kQueueHigh = 128;               // kept pairs buffered before they are handed on
 constexpr int kQueueCap = kQueueHigh + kJT * kJT;   // room for one more whole tile
 constexpr int kCovSample = 1024;              // windows per length for the principal directions
 
@@ -291,69 +295,57 @@ __global__ __launch_bounds__(kBlock) void k_join_gather(const uint32_t *__restri
 
 // ------------------------------------------------------------ the tiles
 
-// The exact stage of a tile's queued pairs (whole wavefront): each pair that
-// is no self pair, not taken by an earlier query's tile and outside the
-// exclusion zone gets the certified Parseval bound from the stored records,
-// and if the bound leaves it able to lower one of its cells below T, the
-// canonical FP64 distance.  Returns (pairs inspected, distances computed) of
-// this lane.
-template <typename FT>
-__device__ __forceinline__ uint2 join_exact(const double *__restrict__ t,
-                                         const uint32_t *__restrict__ cell, uint64_t *P,
-                                         const void *F, const double *__restrict__ mu,
-                                         const double *__restrict__ isig,
-                                         const uint32_t *__restrict__ gval,
-                                         const uint8_t *__restrict__ qf, const uint2 *queue,
-                                         int qn, int64_t pbeg, int64_t cell_base, int excl, int m,
-                                         float sqrt2m, double T) {
-    const int lane = lane_id();
-    uint32_t n_kept = 0, n_ver = 0;
-    for (int base = 0; base < qn; base += kWave) {
-        const int e = base + lane;
-        bool has = false;
-        uint32_t ki = 0, kc = 0;
-        int64_t si = 0, sc = 0;
-        double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0, lim = INFINITY;
-        if (e < qn) {
-            const uint2 pr = queue[e];
-            const int64_t pi_ = pbeg + pr.x, pc_ = pbeg + pr.y;
-            ki = gval[pi_];
-            kc = gval[pc_];
-            if (pc_ != pi_ && !(qf[kc] && pc_ < pi_)) {
-                si = (int64_t)cell[ki] - cell_base;
-                sc = (int64_t)cell[kc] - cell_base;
-                const int64_t gap = si > sc ? si - sc : sc - si;
-                if (gap >= excl) {
-                    Pi = bitsd(P[ki]);
-                    Pc = bitsd(P[kc]);
-                    const double thr = fmin(T, fmax(Pi, Pc));
-                    if (thr > 0.0) {
-                        const float lb = lb_mem<FT>((const FT *)F + (int64_t)ki * kRec,
-                                                    (const FT *)F + (int64_t)kc * kRec, sqrt2m);
-                        if ((double)lb <= T && ((double)lb < Pi || (double)lb < Pc)) {
-                            has = true;
-                            lim = exit_bound(thr);
-                            mui = mu[ki];
-                            isi = isig[ki];
-                            muc = mu[kc];
-                            isc = isig[kc];
-                        }
-                    }
-                }
+// The exact stage of kept pairs, one pair (ki, kc) of indexed windows of one
+// length per lane (whole wavefront; `valid` false on lanes without one).  A
+// pair outside the exclusion zone gets the certified Parseval bound from the
+// stored records, and if the bound leaves it able to lower one of its cells
+// below T, the canonical FP64 distance, which lowers both cells.  The
+// window's loads are issued together (one memory latency before the tests).
+// Returns the distances this lane's pair needed (0 or 1).  kLean: the form
+// with the fewest registers (no record bound, one term per lane per load):
+// a pair the bound would have skipped then has its distance computed and
+// discarded at the exit bound, which leaves every cell as the full form does.
+template <typename FT, bool kLaneForm, bool kLean = false>
+__device__ __forceinline__ uint32_t join_exact(const Req &q, bool valid, uint32_t ki, uint32_t kc,
+                                               int m, int64_t cell_base, float sqrt2m, double T) {
+    bool has = false;
+    int64_t si = 0, sc = 0;
+    double Pi = 0.0, Pc = 0.0, mui = 0.0, isi = 0.0, muc = 0.0, isc = 0.0, lim = INFINITY;
+    if (valid) {
+        si = (int64_t)q.cell[ki] - cell_base;
+        sc = (int64_t)q.cell[kc] - cell_base;
+        Pi = bitsd(q.P[ki]);
+        Pc = bitsd(q.P[kc]);
+        mui = q.mu[ki];
+        isi = q.isig[ki];
+        muc = q.mu[kc];
+        isc = q.isig[kc];
+        const int64_t gap = si > sc ? si - sc : sc - si;
+        const double thr = fmin(T, fmax(Pi, Pc));
+        if (gap >= q.excl && thr > 0.0) {
+            const float lb = kLean ? 0.0f
+                                   : lb_mem<FT>((const FT *)q.F + (int64_t)ki * kRec,
+                                                (const FT *)q.F + (int64_t)kc * kRec, sqrt2m);
+            if ((double)lb <= T && ((double)lb < Pi || (double)lb < Pc)) {
+                has = true;
+                lim = exit_bound(thr);
             }
         }
-        const uint64_t mask = __ballot(has);
-        n_kept += e < qn;
-        if (mask)
-            verify_proposals<false>(mask, SeriesA{t}, t, si, mui, isi, sc, muc, isc, m,
-                                    [&](double dd) {
-                ++n_ver;
-                const unsigned long long db = (unsigned long long)dbits(dd);
-                if (dd < Pi) atomicMin((unsigned long long *)&P[ki], db);
-                if (dd < Pc) atomicMin((unsigned long long *)&P[kc], db);
-            }, lim);
     }
-    return make_uint2(n_kept, n_ver);
+    uint32_t n_ver = 0;
+    const uint64_t mask = __ballot(has);
+    if (mask) {
+        uint64_t *P = q.P;
+        verify_proposals<kLaneForm, kLean ? 1 : kZBatch>(mask, SeriesA{q.t}, q.t, si, mui, isi, sc,
+                                                         muc, isc, m,
+                                    [&](double dd) {
+            ++n_ver;
+            const unsigned long long db = (unsigned long long)dbits(dd);
+            if (dd < Pi) atomicMin((unsigned long long *)&P[ki], db);
+            if (dd < Pc) atomicMin((unsigned long long *)&P[kc], db);
+        }, lim);
+    }
+    return n_ver;
 }
 
 // A block of kJB wavefronts takes kJB consecutive query tiles of 32 sorted
@@ -363,18 +355,25 @@ __device__ __forceinline__ uint2 join_exact(const double *__restrict__ t,
 // flight while the current one goes through the matrix cores and the
 // filter) and read from there by every wavefront, so the kJB query tiles,
 // whose neighbourhoods nearly coincide, share its global traffic.  Every
-// wavefront keeps its own queries, filter terms and queue of kept pairs, and
-// runs the exact stage when its queue fills.
+// wavefront keeps its own queries, filter terms and queue of kept pairs (as
+// window indices (k_q, k_c)).  A full queue is copied to the pair buffer,
+// whose pairs k_join_verify takes after the launch; a wavefront that finds
+// the buffer full runs the exact stage of the rest in place.  The launch
+// covers the blocks [blk0, blk0 + gridDim.x) of the round.
 constexpr int kJB = kJoinBlock;               // query tiles (wavefronts) per block
 constexpr int kJRow = 9;                      // uint4 per LDS operand row (8 + 1: no bank conflicts)
 
 template <typename FT>
-__global__ __launch_bounds__(kJB * kWave) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(kJB * kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restrict__ gkey,
                   const uint32_t *__restrict__ gval, const uint8_t *__restrict__ qf,
                   const uint4 *__restrict__ jop_s, const float4 *__restrict__ jmeta,
-                  const float4 *__restrict__ gp_s, int cb1, int cb2, int cb3, double T) {
+                  const float4 *__restrict__ gp_s, int cb1, int cb2, int cb3, double T,
+                  int64_t blk0, uint2 *__restrict__ pairs, unsigned long long *__restrict__ pcount,
+                  int64_t cap) {
     __shared__ uint2 queue[kJB][kQueueCap];
+    __shared__ uint32_t rowk[kJB][kJT];               // the queries' window indices
+    __shared__ uint32_t ck[2][kJT];                   // the candidates' window indices
     __shared__ float roww[kJB][kJT];                  // the queries' Gram filter terms
     __shared__ float4 rowc[kJB][kJT];                 // the queries' principal coordinates
     __shared__ uint4 cop[2][kJT][kJRow];              // candidate operands, two tiles
@@ -383,12 +382,13 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
     const int tid = threadIdx.x;
     const int wv = tid / kWave;
     const int lane = lane_id();
+    const int64_t gb = blk0 + (int64_t)blockIdx.x;
     int l;
     {
         int lo = 0, hi = q.L - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (gl[mid].blk_base <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+            if (gl[mid].blk_base <= gb) lo = mid; else hi = mid - 1;
         }
         l = lo;
     }
@@ -396,7 +396,7 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
     const LenInfo L = q.len[l];
     const int m = L.m;
     const int64_t pbeg = L.kbase, pend = L.kbase + L.n_index;
-    const int64_t p0 = pbeg + (((int64_t)blockIdx.x - G.blk_base) * kJB + wv) * kJT;
+    const int64_t p0 = pbeg + ((gb - G.blk_base) * kJB + wv) * kJT;
     const int i = lane % kJT, hh = lane / kJT;
     const int64_t pq = p0 + i;
     const bool validq = pq < pend;
@@ -445,6 +445,7 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
     }
     if (hh == 0) {
         roww[wv][i] = a;
+        rowk[wv][i] = kq;
         rowc[wv][i] = isq ? gp_s[pq] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
 
@@ -459,15 +460,27 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
     unsigned long long n_pairs = 0, n_kept = 0, n_ver = 0;
     int qn = 0;                                           // queued pairs (wave-uniform)
 
-    // exact stage for the queued pairs of this wavefront
-    auto flush = [&]() {
+    // hand the queued pairs of this wavefront to the pair buffer: one
+    // reservation for the whole queue; the part past the buffer's end gets
+    // the exact stage here
+    auto spill = [&]() {
         // the queue is written and read by lanes of this wavefront only
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const uint2 c = join_exact<FT>(q.t, q.cell, q.P, q.F, q.mu, q.isig, gval, qf, queue[wv],
-                                       qn, pbeg, L.cell_base, q.excl, m, G.sqrt2m, T);
-        n_kept += c.x;
-        n_ver += c.y;
+        unsigned long long base = 0;
+        if (lane == 0) {
+            base = atomicAdd(pcount, (unsigned long long)qn);
+            n_kept += (unsigned long long)qn;
+        }
+        base = __shfl(base, 0, kWave);
+        const int fit = base >= (unsigned long long)cap
+                            ? 0 : (int)min((unsigned long long)qn, (unsigned long long)cap - base);
+        for (int e = lane; e < fit; e += kWave) pairs[base + e] = queue[wv][e];
+        for (int b = fit; b < qn; b += kWave) {
+            const int e = b + lane;
+            const uint2 pr = e < qn ? queue[wv][e] : make_uint2(0u, 0u);
+            n_ver += join_exact<FT, false, true>(q, e < qn, pr.x, pr.y, m, L.cell_base, G.sqrt2m, T);
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         qn = 0;
@@ -536,26 +549,33 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
     // loads it with one 16-byte part of one candidate per thread (and the
     // coordinates of one candidate on each of the first 32 threads)
     const int ld_c = tid / 8, ld_part = tid % 8;
-    auto load_part = [&](bool have_t, int64_t tc0, int64_t tend, uint4 &op, float4 &cg) {
+    auto load_part = [&](bool have_t, int64_t tc0, int64_t tend, uint4 &op, float4 &cg,
+                         uint32_t &kc) {
         const int64_t pc = tc0 + ld_c;
         op = have_t && pc < tend ? jop_s[pc * 8 + ld_part] : make_uint4(0, 0, 0, 0);
         if (tid < kJT) {
             const int64_t pg = tc0 + tid;
-            cg = have_t && pg < tend ? gp_s[pg] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+            const bool in = have_t && pg < tend;
+            cg = in ? gp_s[pg] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+            kc = in ? gval[pg] : 0u;
         }
     };
-    auto store_part = [&](int buf, const uint4 &op, const float4 &cg) {
+    auto store_part = [&](int buf, const uint4 &op, const float4 &cg, uint32_t kc) {
         cop[buf][ld_c][ld_part] = op;
-        if (tid < kJT) cgp[buf][tid] = cg;
+        if (tid < kJT) {
+            cgp[buf][tid] = cg;
+            ck[buf][tid] = kc;
+        }
     };
 
     bool have = next_run();
-    int64_t tc0 = c0, tend = cend;
+    int64_t tc0 = c0;
     {
         uint4 op;
         float4 cg;
-        load_part(have, tc0, tend, op, cg);
-        store_part(0, op, cg);
+        uint32_t kc = 0;
+        load_part(have, tc0, cend, op, cg, kc);
+        store_part(0, op, cg, kc);
     }
     __syncthreads();
     // the Gram filter terms of the 16 rows this lane holds, in registers for
@@ -571,13 +591,13 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
         const int64_t nc0 = c0, nend = cend;
         uint4 op;
         float4 cg;
-        load_part(have1, nc0, nend, op, cg);
+        uint32_t kcn = 0;
+        load_part(have1, nc0, nend, op, cg, kcn);
         // this tile: operands from LDS (lane (i, hh) holds candidate tc0 + i)
         const bf16x8 bH0 = as_bf16x8(cop[cur][i][hh]), bH1 = as_bf16x8(cop[cur][i][2 + hh]);
         const bf16x8 bL0 = as_bf16x8(cop[cur][i][4 + hh]), bL1 = as_bf16x8(cop[cur][i][6 + hh]);
         const float4 gc = cgp[cur][i];
         const float bj = fabsf(gc.w);
-        const bool qc = gc.w != INFINITY && signbit(gc.w);
         f32x16 acc = {};
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH0, bH0, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aH1, bH1, acc, 0, 0, 0);
@@ -586,49 +606,57 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL0, bH0, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aL1, bH1, acc, 0, 0, 0);
         n_pairs += 16;
-        // keep (row, candidate) unless the Gram bound or a coordinate rules it
-        // out, or the candidate is a query earlier in the order (its tile
-        // takes the pair), or it is the row itself.  Positions relative to
-        // the query tile (p0) and to the length (pbeg) fit 32 bits.
-        const int64_t pc = tc0 + i;
-        const int pcr = (int)(pc - p0);
-        const uint32_t pcl = (uint32_t)(pc - pbeg), p0l = (uint32_t)(p0 - pbeg);
-        // the Gram test of all 16 rows first: most tiles keep nothing
-        bool anyg = false;
+        // the Gram test of the 16 rows this lane holds, as a bit mask (bit r:
+        // row 8 (r / 4) + 4 hh + r % 4); most tiles keep nothing
+        uint32_t km = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) anyg |= acc[r] >= rw[r] + bj;
-        if (__ballot(anyg)) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                // the rows of the 32 x 32 result this lane holds: 8 (r / 4) + 4 hh + r % 4
-                const int row = 8 * (r / 4) + 4 * hh + (r % 4);
-                const bool gram = acc[r] >= rw[r] + bj;
-                if (__ballot(gram) == 0) continue;
+        for (int r = 0; r < 16; ++r) km |= (acc[r] >= rw[r] + bj ? 1u : 0u) << r;
+        if (__ballot(km != 0u)) {
+            // keep (row, candidate) unless a coordinate rules it out, the
+            // candidate is a query earlier in the order (its tile takes the
+            // pair) or it is the row itself (positions relative to the query
+            // tile p0); each lane walks only its own passing rows
+            const int pcr = (int)(tc0 + i - p0);
+            const bool qc = gc.w != INFINITY && signbit(gc.w);
+            uint32_t kk = 0;
+            for (uint32_t b = km; b != 0u; b &= b - 1u) {
+                const int r = __builtin_ctz(b);
+                const int row = 8 * (r >> 2) + 4 * hh + (r & 3);
                 const float4 rc = rowc[wv][row];
-                const bool keep = gram && fabsf(rc.x - gc.x) <= G.rp && fabsf(rc.y - gc.y) <= G.rp &&
-                                  fabsf(rc.z - gc.z) <= G.rp && pcr != row && !(qc && pcr < row);
-                const uint64_t bal = __ballot(keep);
-                if (bal == 0) continue;
-                if (keep)
-                    queue[wv][qn + __popcll(bal & lanemask_lt())] =
-                        make_uint2(p0l + (uint32_t)row, pcl);
-                qn += __popcll(bal);
+                if (fabsf(rc.x - gc.x) <= G.rp && fabsf(rc.y - gc.y) <= G.rp &&
+                    fabsf(rc.z - gc.z) <= G.rp && pcr != row && !(qc && pcr < row))
+                    kk |= 1u << r;
             }
+            // queue positions: an exclusive prefix sum of the counts
+            const int cnt = __popc(kk);
+            int pre = cnt;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int v = __shfl_up(pre, off, kWave);
+                if (lane >= off) pre += v;
+            }
+            const int total = __shfl(pre, kWave - 1, kWave);
+            int pos = qn + pre - cnt;
+            const uint32_t kcand = ck[cur][i];
+            for (uint32_t b = kk; b != 0u; b &= b - 1u) {
+                const int r = __builtin_ctz(b);
+                queue[wv][pos++] = make_uint2(rowk[wv][8 * (r >> 2) + 4 * hh + (r & 3)], kcand);
+            }
+            qn += total;
+            if (qn > kQueueHigh) spill();
         }
-        if (qn > kQueueHigh) flush();
         // stage the next tile; after the barrier it is the current one
-        store_part(cur ^ 1, op, cg);
+        store_part(cur ^ 1, op, cg, kcn);
         __syncthreads();
         cur ^= 1;
         have = have1;
         tc0 = nc0;
-        tend = nend;
         if (have) {
             c0 += kJT;
             have1 = next_run();
         }
     }
-    if (qn > 0) flush();
+    if (qn > 0) spill();
     // statistics: one atomic per wavefront
     for (int off = kWave / 2; off > 0; off >>= 1) {
         n_pairs += __shfl_xor(n_pairs, off, kWave);
@@ -640,6 +668,33 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
         if (n_kept) atomicAdd(&q.counters[C_JOIN_CAND], n_kept);
         if (n_ver) atomicAdd(&q.counters[C_JOIN_VER], n_ver);
     }
+}
+
+// The exact stage of the pairs in the buffer (the first min(*pcount, cap)
+// entries), one pair per lane, the wavefronts striding over the buffer.
+// Pairs of one length sit together in the buffer (a queue holds one
+// length), so a wavefront's pairs mostly share their window length.
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_join_verify(Req q, const GridLen *__restrict__ gl,
+                                                        const uint2 *__restrict__ pairs,
+                                                        const unsigned long long *__restrict__ pcount,
+                                                        int64_t cap, double T) {
+    const int64_t n = min((int64_t)*pcount, cap);
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    uint32_t n_ver = 0;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < n;
+         base += stride) {
+        const int64_t e = base + lane;
+        const bool valid = e < n;
+        const uint2 pr = valid ? pairs[e] : make_uint2(0u, 0u);
+        const int l = valid ? find_len_k(q.len, q.L, (int64_t)pr.x) : 0;
+        const LenInfo &L = q.len[l];
+        n_ver += join_exact<FT, true>(q, valid, pr.x, pr.y, L.m, L.cell_base, gl[l].sqrt2m, T);
+    }
+    unsigned long long v = n_ver;
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (lane == 0 && v) atomicAdd(&q.counters[C_JOIN_VER], v);
 }
 
 // ------------------------------------------------------------ launchers
@@ -673,15 +728,31 @@ void launch_join_gather(const uint32_t *gval, const uint4 *jop, const float4 *gp
 
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop_s,
-                       const float4 *jmeta, const float4 *gp_s, int64_t nblocks, int cb1, int cb2,
-                       int cb3, double T, hipStream_t s) {
+                       const float4 *jmeta, const float4 *gp_s, int64_t blk0, int64_t nblocks,
+                       int cb1, int cb2, int cb3, double T, uint2 *pairs,
+                       unsigned long long *pcount, int64_t cap, hipStream_t s) {
     if (nblocks <= 0) return;
     if (precision == 0)
         hipLaunchKernelGGL(k_join_tiles<double>, dim3((unsigned)nblocks), dim3(kJB * kWave), 0, s,
-                           q, gl, gkey, gval, qf, jop_s, jmeta, gp_s, cb1, cb2, cb3, T);
+                           q, gl, gkey, gval, qf, jop_s, jmeta, gp_s, cb1, cb2, cb3, T, blk0,
+                           pairs, pcount, cap);
     else
         hipLaunchKernelGGL(k_join_tiles<float>, dim3((unsigned)nblocks), dim3(kJB * kWave), 0, s,
-                           q, gl, gkey, gval, qf, jop_s, jmeta, gp_s, cb1, cb2, cb3, T);
+                           q, gl, gkey, gval, qf, jop_s, jmeta, gp_s, cb1, cb2, cb3, T, blk0,
+                           pairs, pcount, cap);
+}
+
+void launch_join_verify(int precision, const Req &q, const GridLen *gl, const uint2 *pairs,
+                        const unsigned long long *pcount, int64_t cap, double T, hipStream_t s) {
+    // enough wavefronts to keep every SIMD busy with eight, each striding
+    const int64_t want = (cap + kBlock - 1) / kBlock;
+    const unsigned nb = (unsigned)(want < 2048 ? want : 2048);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_join_verify<double>, dim3(nb), dim3(kBlock), 0, s, q, gl, pairs,
+                           pcount, cap, T);
+    else
+        hipLaunchKernelGGL(k_join_verify<float>, dim3(nb), dim3(kBlock), 0, s, q, gl, pairs,
+                           pcount, cap, T);
 }
 
 }  // namespace pmp

@@ -195,24 +195,25 @@ struct SeriesA {
     __device__ __forceinline__ double operator()(int64_t x) const { return t[x]; }
 };
 
-template <class A>
+template <int kB = kZBatch, class A>
 __device__ __forceinline__ double group_zdist_a(A qa, const double *__restrict__ t, int64_t a,
                                                 double mua, double ia, int64_t b, double mub,
                                                 double ib, int m, double lim2 = INFINITY) {
 #pragma clang fp contract(off)
     double acc = 0.0;
-    // kZBatch terms per lane are loaded before they are summed (in order), so
-    // that a window of up to kZBatch * kGroup samples costs one memory latency
-    for (int r0 = lane_id() & (kGroup - 1); r0 < m; r0 += kZBatch * kGroup) {
-        double xa[kZBatch], xb[kZBatch];
+    // kB terms per lane are loaded before they are summed (in order), so that
+    // a window of up to kB * kGroup samples costs one memory latency (kB = 1:
+    // the fewest registers; the sum and its order are the same for any kB)
+    for (int r0 = lane_id() & (kGroup - 1); r0 < m; r0 += kB * kGroup) {
+        double xa[kB], xb[kB];
 #pragma unroll
-        for (int u = 0; u < kZBatch; ++u) {
+        for (int u = 0; u < kB; ++u) {
             const int r = r0 + u * kGroup;
             xa[u] = r < m ? qa(a + r) : 0.0;
             xb[u] = r < m ? t[b + r] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kZBatch; ++u) {
+        for (int u = 0; u < kB; ++u) {
             if (r0 + u * kGroup < m) {
                 const double za = (xa[u] - mua) * ia;
                 const double zb = (xb[u] - mub) * ib;
@@ -224,7 +225,7 @@ __device__ __forceinline__ double group_zdist_a(A qa, const double *__restrict__
         // rounding is monotone), so once their total reaches lim2 the
         // finished sum would too; the group decides together (all its lanes
         // compute the same total)
-        if (lim2 != INFINITY && (r0 | (kGroup - 1)) + 1 + (kZBatch - 1) * kGroup < m) {
+        if (lim2 != INFINITY && (r0 | (kGroup - 1)) + 1 + (kB - 1) * kGroup < m) {
             double sp = acc;
 #pragma unroll
             for (int off = 1; off < kGroup; off <<= 1) sp += __shfl_xor(sp, off, kGroup);
@@ -398,7 +399,7 @@ __device__ __forceinline__ float lb_mem(const FT *__restrict__ fq, const FT *__r
 // one per group of kGroup lanes (group_zdist).  Both give the same bits.
 // `on_result(d)` runs on the proposing lane with its snapped distance (+inf
 // when the sum stopped early).
-template <bool kLaneForm = true, class A, typename F>
+template <bool kLaneForm = true, int kB = kZBatch, class A, typename F>
 __device__ __forceinline__ void verify_proposals(uint64_t mask, A qa, const double *__restrict__ t,
                                                  int64_t a, double mua, double ia, int64_t b,
                                                  double mub, double ib, int m, F &&on_result,
@@ -438,7 +439,7 @@ __device__ __forceinline__ void verify_proposals(uint64_t mask, A qa, const doub
         const double glim = __shfl(lim2, my, kWave);
         int gm = __shfl(m, my, kWave);
         if (!live) gm = 0;
-        const double d = snap(group_zdist_a(qa, t, ga, gmua, gia, gb, gmub, gib, gm, glim));
+        const double d = snap(group_zdist_a<kB>(qa, t, ga, gmua, gia, gb, gmub, gib, gm, glim));
         // hand each result back to its proposing lane
 #pragma unroll
         for (int g = 0; g < kPerRound; ++g) {
@@ -589,11 +590,17 @@ void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int c
 // sorted order
 void launch_join_gather(const uint32_t *gval, const uint4 *jop, const float4 *gp, int64_t n,
                         uint4 *jop_s, float4 *gp_s, hipStream_t s);
-// one block of kJoinBlock query tiles per GridLen block, nblocks in all
+// one block of kJoinBlock query tiles per GridLen block: the blocks
+// [blk0, blk0 + nblocks) of the round; kept pairs go to `pairs` (capacity
+// cap, fill count *pcount), or are verified in place once it is full
 void launch_join_tiles(int precision, const Req &q, const GridLen *gl, const uint32_t *gkey,
                        const uint32_t *gval, const uint8_t *qf, const uint4 *jop_s,
-                       const float4 *jmeta, const float4 *gp_s, int64_t nblocks, int cb1, int cb2,
-                       int cb3, double T, hipStream_t s);
+                       const float4 *jmeta, const float4 *gp_s, int64_t blk0, int64_t nblocks,
+                       int cb1, int cb2, int cb3, double T, uint2 *pairs,
+                       unsigned long long *pcount, int64_t cap, hipStream_t s);
+// the exact stage of the first min(*pcount, cap) pairs of the buffer
+void launch_join_verify(int precision, const Req &q, const GridLen *gl, const uint2 *pairs,
+                        const unsigned long long *pcount, int64_t cap, double T, hipStream_t s);
 void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
                  unsigned long long *out_min, unsigned long long *out_arg, hipStream_t s);
 void launch_stream_basis(const SAnchor *anc, int na, int64_t elems, double *basis,

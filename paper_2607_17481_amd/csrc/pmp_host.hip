@@ -418,6 +418,9 @@ struct Bufs {
     uint32_t *jk, *jv, *jk2, *jv2;
     uint4 *jop_s;              // join operands and coordinates in grid order
     float4 *gp_s;
+    uint2 *jpairs;             // the join's kept pairs (k_q, k_c), jcap of them
+    unsigned long long *jcount;
+    int64_t jcap;
     // emit stage: cell -> k map, partner hints, sieve segments and
     // directions, completion seeds
     uint32_t *kmap, *hint, *scnt, *stotal, *sseg, *seeds;
@@ -471,6 +474,10 @@ static void carve1(Arena &a, Bufs &b, const Plan &p, int k) {
 
 static bool needs_kmap(const Opt &o) { return o.stride > 1; }
 
+// Kept pairs of the join buffered between its tiles and its exact stage:
+// two per indexed window (16 bytes a window), at least 2^16.
+static int64_t join_pair_cap(int64_t N) { return std::max<int64_t>(int64_t(1) << 16, 2 * N); }
+
 static void carve2(Arena &a, Bufs &b, const Plan &p, const Opt &o, int k) {
     const int precision = o.precision;
     const int64_t N = std::max<int64_t>(p.N, 1);
@@ -498,6 +505,9 @@ static void carve2(Arena &a, Bufs &b, const Plan &p, const Opt &o, int k) {
     b.jv = take<uint32_t>(a, N);
     b.jk2 = take<uint32_t>(a, N);
     b.jv2 = take<uint32_t>(a, N);
+    b.jcap = join_pair_cap(N);
+    b.jpairs = take<uint2>(a, b.jcap);
+    b.jcount = take<unsigned long long>(a, 1);
     b.sel_cnt = take<uint32_t>(a, select_blocks(N) + 1);
     b.selblk = (char *)a.take(select_block_bytes(need));
     b.sel = (SelState *)b.selblk;
@@ -862,6 +872,7 @@ static int run_pipeline(Run &R, Arena &ar) {
     if (p.N != (int64_t)toff[p.ntiles]) return fail(PMP_EINTERNAL, "index count mismatch");
     carve2(ar, b, p, o, R.k);
     if (ar.off > ar.cap) return fail(PMP_ENOMEM, "workspace too small (%zu < %zu)", ar.cap, ar.off);
+    if (R.dbg && R.dbg->join_pair_cap > 0) b.jcap = std::min(b.jcap, R.dbg->join_pair_cap);
     const int64_t N = p.N;
 
     // ---- per-request constants (the host vectors live until the next
@@ -1081,8 +1092,36 @@ static int run_pipeline(Run &R, Arena &ar) {
             radix_sort_pairs(b.jk, b.jv, b.jk2, b.jv2, Nq, 0, p.len_bits + cb1 + cb2 + cb3,
                              b.sort_tmp, s);
             launch_join_gather(b.jv, b.jop, b.gp, Nq, b.jop_s, b.gp_s, s);
-            launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop_s, b.jmeta, b.gp_s,
-                              nbq, cb1, cb2, cb3, Teff, s);
+            // the tiles in chunks of blocks, each followed by the exact stage
+            // of the pairs it kept (a kernel of its own, at full occupancy).
+            // A chunk is sized to fill at most half the pair buffer at the
+            // largest rate of kept pairs per block seen so far in the round
+            // (the first at 16 pairs per window); a wavefront that still
+            // finds the buffer full verifies the rest of its pairs itself.
+            launch_fill_u64((uint64_t *)b.jcount, 1, 0ull, s);
+            {
+                const int64_t first = std::max<int64_t>(64, b.jcap / (2 * 16 * win_per_blk));
+                double rate = 0.0;                       // kept pairs per block
+                for (int64_t b0 = 0; b0 < nbq;) {
+                    const int64_t lim =
+                        rate > 0.0 ? std::max<int64_t>(64, (int64_t)std::min(0.5 * (double)b.jcap / rate, 1e15))
+                                   : first;
+                    const int64_t nb = std::min(nbq - b0, lim);
+                    launch_join_tiles(o.precision, q, b.gl, b.jk, b.jv, b.qf, b.jop_s, b.jmeta,
+                                      b.gp_s, b0, nb, cb1, cb2, cb3, Teff, b.jpairs, b.jcount,
+                                      b.jcap, s);
+                    launch_join_verify(o.precision, q, b.gl, b.jpairs, b.jcount, b.jcap, Teff, s);
+                    HIPCHK(hipGetLastError());
+                    b0 += nb;
+                    if (b0 < nbq) {
+                        unsigned long long kept = 0;
+                        HIPCHK(hipMemcpyAsync(&kept, b.jcount, 8, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        rate = std::max(rate, (double)(kept + 1) / (double)nb);
+                        launch_fill_u64((uint64_t *)b.jcount, 1, 0ull, s);
+                    }
+                }
+            }
             HIPCHK(hipGetLastError());
             rc = select_topk(p, b, R.k, s, acc);   // synchronizes: gl may be rewritten next
             if (rc) return rc;
@@ -1253,6 +1292,8 @@ static int run_device(const double *d_series, int64_t n, int32_t m_min, int32_t 
     if (dbg && dbg->size != sizeof(pmp_debug)) return fail(PMP_EINVAL, "pmp_debug.size mismatch");
     if (dbg && !(dbg->t_start_scale >= 0.0 && dbg->t_start_scale < 1.0))
         return fail(PMP_EINVAL, "pmp_debug.t_start_scale must lie in [0, 1)");
+    if (dbg && dbg->join_pair_cap < 0)
+        return fail(PMP_EINVAL, "pmp_debug.join_pair_cap must be >= 0");
     int rc = check_args(n, m_min, m_max, k, excl, budget);
     if (rc) return rc;
     Run R{};

@@ -63,7 +63,8 @@ class Debug(C.Structure):
                 ("lengths", C.c_void_p), ("depth", C.c_void_p), ("indexed", C.c_void_p),
                 ("mu", C.c_void_p), ("sigma", C.c_void_p), ("profile_pass", C.c_void_p),
                 ("profile_final", C.c_void_p), ("features", C.c_void_p), ("keys", C.c_void_p),
-                ("perm", C.c_void_p), ("bucket_start", C.c_void_p), ("t_start_scale", C.c_double)]
+                ("perm", C.c_void_p), ("bucket_start", C.c_void_p), ("t_start_scale", C.c_double),
+                ("join_pair_cap", C.c_int64)]
 
 
 class Timing(C.Structure):

@@ -478,6 +478,35 @@ def test_queried_workspace_suffices_for_large_k_at_budget_one(gpu, oracle):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_join_pair_buffer_overflow(gpu, ws, prec):
+    """The threshold join's kept pairs pass through a bounded buffer to their
+    own exact-stage kernel; pairs that find it full are verified by the tiles
+    in place.  With the buffer capped far below what the join keeps (one
+    pair, then an eighth of the uncapped count), the top-k must equal the
+    uncapped run's and the stored oracle top-k (Sec. 3.6: the join verifies
+    every kept pair either way)."""
+    g = golden("ecg5k_top20")
+    t = golden_series(g)
+    args = (gpu, ws, t, g["m_min"], g["m_max"], g["exclusion"], g["k"])
+    dbg = gpu.Debug()
+    dbg.size = C.sizeof(gpu.Debug)
+    base, st0 = run(*args, debug=dbg, m_step=g["m_step"], precision=PRECS[prec])
+    print(f"{prec} uncapped: kept {st0['join_candidates']} verified {st0['join_verified']}")
+    assert st0["join_candidates"] >= 64
+    for cap in (1, st0["join_candidates"] // 8):
+        dbg.join_pair_cap = cap
+        res, st = run(*args, debug=dbg, m_step=g["m_step"], precision=PRECS[prec])
+        print(f"{prec} cap {cap}: kept {st['join_candidates']} verified {st['join_verified']}")
+        assert res == base
+        ok, msg = parity.canonical_equal(res, g["top"])
+        assert ok, msg
+    dbg.join_pair_cap = -1
+    with pytest.raises(gpu.PMPError) as e:
+        run(*args, debug=dbg, m_step=g["m_step"], precision=PRECS[prec])
+    assert e.value.code == gpu.PMP_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_threshold_loop_past_first_round(gpu, ws, oracle, prec):
     """The certificate's threshold loop (Sec. 3.6; the greedy prefix up to T
     depends only on cells at or below T) started at a quarter of the one-pass
