@@ -39,6 +39,10 @@ WORKLOADS = {
     "tiny": ("random_walk_planted", 4000, synth.SEED_TINY, 32, 82, 1, 64, 20),
 }
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+# occupancy target alpha of the timed calls, the served requests and the
+# stream (the budget R = gamma * alpha; a speed-only constant, Prop. 2:
+# alpha 4 to 8 measured fastest with the default anchor stride)
+ALPHA = 8
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
 
@@ -251,7 +255,7 @@ def serving_run(precision, reqs, series, rate, slots, budget, progress=False, de
             delay = r.arrival_s / rate - (time.perf_counter() - t0) if rate else 0.0
             if delay > 0:
                 time.sleep(delay)
-            ids.append(srv.submit(t, r.m_min, r.m_max, r.k, r.exclusion, 16, opts))
+            ids.append(srv.submit(t, r.m_min, r.m_max, r.k, r.exclusion, ALPHA, opts))
         th.join()
     lat = np.array([tm["end_s"] - tm["submit_s"] for tm in results])
     span = max(tm["end_s"] for tm in results) - min(tm["submit_s"] for tm in results)
@@ -344,7 +348,7 @@ def streaming_bench(workload, n=STREAM_DEFAULT["n"], chunk=STREAM_DEFAULT["chunk
     from paper_2607_17481_amd import pmp
     gen, _, seed, m_min, m_max, step, excl, k = WORKLOADS[workload]
     t = make_series(workload)[:n]
-    with pmp.Stream(len(t), m_min, m_max, k, excl, 16, 0, pmp.options(m_step=step)) as s:
+    with pmp.Stream(len(t), m_min, m_max, k, excl, ALPHA, 0, pmp.options(m_step=step)) as s:
         t0 = time.perf_counter()
         for x in range(0, len(t), chunk):
             s.append(t[x:x + chunk])
@@ -356,7 +360,7 @@ def streaming_bench(workload, n=STREAM_DEFAULT["n"], chunk=STREAM_DEFAULT["chunk
         ex, st = s.exact(stats=True)
         ex_ms = (time.perf_counter() - t1) * 1e3
     td = torch.from_numpy(t).cuda()
-    ref, _ = pmp.run_device(td, m_min, m_max, k, excl, 16, pmp.options(m_step=step),
+    ref, _ = pmp.run_device(td, m_min, m_max, k, excl, ALPHA, pmp.options(m_step=step),
                             pmp.Workspace("cuda:0"))
     return {"n": len(t), "batch": info["batch"], "anchors": info["lengths"],
             "samples_per_s": len(t) / el, "anchor_cells_per_s": anchor_cells / el,
@@ -406,15 +410,18 @@ EMIT_SWEEP = (
     + [(f"rounds {r}", dict(complete_rounds=r)) for r in (0, 1, 8)]
     + [(f"radii {dm},{dp}", dict(complete_dm=dm, complete_dp=dp)) for dm, dp in ((2, 1), (12, 8))]
 )
+# anchor stride and occupancy target together (both speed-only constants)
+GRID_SWEEP = {"stride": (6, 8, 12, 16, 24), "alpha": (4, 8, 16)}
 
 
-def param_sweep(workload, precision, steps=2, emit=False):
+def param_sweep(workload, precision, steps=2, emit=False, grid=False):
     """Runtime against the occupancy target alpha (spectral width calibrated)
     and against the spectral width K (alpha = 16), and at alpha = 4, K = 4
     (the paper's maximum-performance constants that apply here; its P_max
     has no counterpart here); with `emit`, against the anchor stride, the
     sieve width, the completion round cap and radii instead (each varied
-    alone from the defaults).  The exact top-k is the same in every
+    alone from the defaults); with `grid`, over the anchor stride and alpha
+    together.  The exact top-k is the same in every
     configuration (Prop. 2 for K; the certificate for the rest); each run is
     checked against the default one."""
     import torch
@@ -451,11 +458,19 @@ def param_sweep(workload, precision, steps=2, emit=False):
         return r, [(x.i, x.j, x.m, x.dist) for x in res]
 
     base, ref = run(16, 0, "default")
-    out = {"metric": "runtime against " + ("the emit-stage constants" if emit else "alpha and K"),
+    out = {"metric": "runtime against " + ("the emit-stage constants" if emit else
+                                           "the anchor stride and alpha" if grid else "alpha and K"),
            "workload": workload, "precision": precision, "cells": cells, "steps": steps,
            "default": base}
     same = True
-    if emit:
+    if grid:
+        out["runs"] = []
+        for sv in GRID_SWEEP["stride"]:
+            for a in GRID_SWEEP["alpha"]:
+                r, top = run(a, 0, f"stride {sv} alpha {a}", anchor_stride=sv)
+                same &= top == ref
+                out["runs"].append(r)
+    elif emit:
         out["runs"] = []
         for label, kw in EMIT_SWEEP:
             r, top = run(16, 0, label, **kw)
@@ -506,6 +521,8 @@ def main():
                     help="capacity (requests/s) to take instead of measuring it")
     ap.add_argument("--param-sweep", action="store_true",
                     help="only run the alpha / K sweep on --workload")
+    ap.add_argument("--grid-sweep", action="store_true",
+                    help="only run the anchor stride x alpha sweep on --workload")
     ap.add_argument("--emit-sweep", action="store_true",
                     help="only run the anchor stride / sieve / completion sweep on --workload")
     args = ap.parse_args()
@@ -524,8 +541,8 @@ def main():
                    loads=tuple(float(x) for x in args.sweep_loads.split(",")))
         serving_sweep(cfg, args.sweep_capacity)
         return
-    if args.param_sweep or args.emit_sweep:
-        param_sweep(args.workload, args.precision, emit=args.emit_sweep)
+    if args.param_sweep or args.emit_sweep or args.grid_sweep:
+        param_sweep(args.workload, args.precision, emit=args.emit_sweep, grid=args.grid_sweep)
         return
 
     import torch
@@ -541,14 +558,14 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     for _ in range(args.warmup):
-        pmp.run_device(td, m_min, m_max, k, excl, 16, opts, ws, stream)
+        pmp.run_device(td, m_min, m_max, k, excl, ALPHA, opts, ws, stream)
     torch.cuda.synchronize()
     stats = []
     step_ms = []          # each call returns with its results in host memory
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        res, st = pmp.run_device(td, m_min, m_max, k, excl, 16, opts, ws, stream)
+        res, st = pmp.run_device(td, m_min, m_max, k, excl, ALPHA, opts, ws, stream)
         step_ms.append((time.perf_counter() - s0) * 1e3)
         stats.append(st)
     torch.cuda.synchronize()
@@ -599,7 +616,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "generator": gen, "n": n, "m_min": m_min,
                    "m_max": m_max, "m_step": step, "exclusion": excl, "k": k,
-                   "cells": cells, "precision": args.precision, "budget_alpha": 16},
+                   "cells": cells, "precision": args.precision, "budget_alpha": ALPHA,
+                   "anchor_stride": opts.anchor_stride},
         "onepass_ms": avg("ms_onepass"),
         "exact_ms": avg("ms_total"),
         "phase_ms": {p: avg("ms_" + p) for p in ("sketch", "sort", "probe", "complete", "join",
@@ -628,13 +646,13 @@ def main():
             if prec == PREC[args.precision]:
                 continue
             o2 = pmp.options(m_step=step, precision=prec)
-            pmp.run_device(td, m_min, m_max, k, excl, 16, o2, ws, stream)
+            pmp.run_device(td, m_min, m_max, k, excl, ALPHA, o2, ws, stream)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             ms2 = []
             for _ in range(args.steps):
                 s1 = time.perf_counter()
-                r2, s2 = pmp.run_device(td, m_min, m_max, k, excl, 16, o2, ws, stream)
+                r2, s2 = pmp.run_device(td, m_min, m_max, k, excl, ALPHA, o2, ws, stream)
                 ms2.append((time.perf_counter() - s1) * 1e3)
             torch.cuda.synchronize()
             el2 = time.perf_counter() - t1

@@ -89,8 +89,9 @@ typedef struct {
     int32_t  anchor_stride;   /* s: the one pass probes every s-th length of
                                  the list and the last; the lengths between
                                  are re-cut from their neighbours' partners;
-                                 default 6 (the paper's maximum-performance
-                                 stride), 1 = every length                    */
+                                 default 16 (the paper's maximum-performance
+                                 stride is 6; on this GPU the step keeps
+                                 getting faster past it), 1 = every length    */
     int32_t  sieve_width;     /* w of the hot-class sieve over buckets of more
                                  than R entries, default 0 = off (the paper
                                  uses 8; here it costs time and lowers none

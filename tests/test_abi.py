@@ -35,11 +35,11 @@ def test_default_options_are_the_paper_constants():
     assert o.size == C.sizeof(pmp.Options)
     assert (o.m_step, o.signature_bits, o.gamma, o.probe_ref_depth, o.certify) == (1, 24, 8, 12, 1)
     assert o.spectral_width == 0 and o.precision == 0
-    # refinement radii (6, 4) and at most eight rounds (Sec. 4 constants); the
-    # anchor stride of the paper's maximum-performance setting (6) and the
-    # sieve off, both measured faster with the same certified result
+    # refinement radii (6, 4) and at most eight rounds (Sec. 4 constants); an
+    # anchor stride of 16 (the paper's maximum-performance setting is 6) and
+    # the sieve off, both measured faster with the same certified result
     assert (o.anchor_stride, o.sieve_width, o.complete_dm, o.complete_dp, o.complete_rounds) == \
-        (6, 0, 6, 4, 8)
+        (16, 0, 6, 4, 8)
 
 
 def test_workspace_query_and_argument_checks():

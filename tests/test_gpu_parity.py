@@ -300,7 +300,7 @@ def test_result_independent_of_width_budget_seed_precision(gpu, ws, oracle):
                dict(seed=1), dict(seed=99), dict(precision=1), dict(precision=2),
                dict(signature_bits=8), dict(gamma=1), dict(probe_cap=0),
                dict(anchor_stride=1), dict(anchor_stride=2), dict(anchor_stride=3),
-               dict(sieve_width=8), dict(complete_rounds=0), dict(sieve_width=8, complete_rounds=0),
+               dict(anchor_stride=6), dict(sieve_width=8), dict(complete_rounds=0), dict(sieve_width=8, complete_rounds=0),
                dict(anchor_stride=4, sieve_width=32, complete_rounds=1, complete_dm=0,
                     complete_dp=0)]:
         for budget in (4, 16, 64):
