@@ -147,9 +147,10 @@ def algorithmic_bytes(n, lengths, st, fs):
     # anchors exist), and per indexed window its cell, mu, 1/sigma, P and
     # record
     sketch = rd + (4 * cells if st["anchors"] < len(lengths) else 0) + nx * (4 + 8 + 8 + 8 + REC * fs)
-    # the keys kernel reads the record back and writes the key word (8) and
-    # the sort key and value (4 + 4)
-    keys = nx * (REC * fs + 8 + 4 + 4)
+    # the keys kernel, at the anchor lengths' indexed windows (the only ones
+    # indexed), reads the record back and writes the key word (8) and the
+    # sort key and value (4 + 4)
+    keys = st.get("probe_queries", nx) * (REC * fs + 8 + 4 + 4)
     # per query (an indexed window of an anchor length): its state; per
     # inspected candidate: slot, P, record; per
     # verified pair: the candidate's moments and the two cell updates (the

@@ -22,7 +22,9 @@ typedef struct {
     int32_t  K;             /* out: spectral width used (Sec. 3.2 calibration) */
     /* host arrays with one entry per length */
     int32_t *lengths;       /* out: window lengths                              */
-    int32_t *depth;         /* out: directory depth d (Sec. 3.4, Prop. 4)       */
+    int32_t *depth;         /* out: directory depth d (Sec. 3.4, Prop. 4); 0
+                               at the lengths between anchors, which have no
+                               directory                                       */
     int64_t *indexed;       /* out: non-constant windows of the length          */
     /* device arrays */
     double  *mu;            /* [cells] window mean (two-pass, Sec. 3.2)         */
@@ -39,8 +41,11 @@ typedef struct {
     uint64_t *keys;         /* [cells] key word: bits 0..B-1 the SimHash
                                signature (paper bit 1 = bit B-1), bits 24..63
                                the Hamming-1 probe bit order, 5 bits each;
-                               all ones for constant windows                   */
-    uint32_t *perm;         /* [sum indexed] bucket order: slot -> cell         */
+                               all ones for constant windows and at the
+                               lengths between anchors (only anchor lengths
+                               are indexed, Sec. 3.3)                          */
+    uint32_t *perm;         /* [indexed windows of the anchor lengths] bucket
+                               order: slot -> cell                             */
     uint32_t *bucket_start; /* [sum 2^depth + 1] first slot of every bucket     */
     /* in: 0 = off.  A value in (0, 1) starts the certificate's threshold
        loop at that fraction of the one-pass threshold T.  The result stays

@@ -489,8 +489,8 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
     // the block's candidate runs (one per grid row next to a query's cell);
     // every decision below is uniform over the block, so that every
     // wavefront passes the same barriers
-    int c1p = max(c1min - 1, 0) - 1;
-    const int c1end = min(c1max + 1, (int)mask1);
+    int c1p = max(c1min - kJoinNb, 0) - 1;
+    const int c1end = min(c1max + kJoinNb, (int)mask1);
     int64_t c0 = 0, cend = 0;
     int c2p = 0, c2end = -1;                              // three coordinates: the row's c2 range
     // move [c0, cend) to the next non-empty run once the current one is used
@@ -502,20 +502,20 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
             while (c0 >= cend && (c2p < c2end || c1p < c1end)) {
                 if (c2p >= c2end) {
                     ++c1p;
-                    const bool near1 = isq && abs(c1q - c1p) <= 1;
+                    const bool near1 = isq && abs(c1q - c1p) <= kJoinNb;
                     int lo2, hi2;
-                    block_minmax(wave_min_i(near1 ? max(c2q - 1, 0) : INT_MAX),
-                                 wave_max_i(near1 ? min(c2q + 1, (int)mask2) : -1), lo2, hi2);
+                    block_minmax(wave_min_i(near1 ? max(c2q - kJoinNb, 0) : INT_MAX),
+                                 wave_max_i(near1 ? min(c2q + kJoinNb, (int)mask2) : -1), lo2, hi2);
                     if (lo2 > hi2) continue;
                     c2p = lo2 - 1;
                     c2end = hi2;
                     continue;
                 }
                 ++c2p;
-                const bool near = isq && abs(c1q - c1p) <= 1 && abs(c2q - c2p) <= 1;
+                const bool near = isq && abs(c1q - c1p) <= kJoinNb && abs(c2q - c2p) <= kJoinNb;
                 int c3lo, c3hi;
-                block_minmax(wave_min_i(near ? max(c3q - 1, 0) : INT_MAX),
-                             wave_max_i(near ? min(c3q + 1, (int)mask3) : -1), c3lo, c3hi);
+                block_minmax(wave_min_i(near ? max(c3q - kJoinNb, 0) : INT_MAX),
+                             wave_max_i(near ? min(c3q + kJoinNb, (int)mask3) : -1), c3lo, c3hi);
                 if (c3lo > c3hi) continue;
                 const uint32_t rk = lbits | ((uint32_t)c1p << (cb2 + cb3)) | ((uint32_t)c2p << cb3);
                 c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c3lo);
@@ -533,10 +533,10 @@ void k_join_tiles(Req q, const GridLen *__restrict__ gl, const uint32_t *__restr
         } else {
             while (c0 >= cend && c1p < c1end) {
                 ++c1p;
-                const bool near = isq && abs(c1q - c1p) <= 1;
+                const bool near = isq && abs(c1q - c1p) <= kJoinNb;
                 int c2lo, c2hi;
-                block_minmax(wave_min_i(near ? max(c2q - 1, 0) : INT_MAX),
-                             wave_max_i(near ? min(c2q + 1, (int)mask2) : -1), c2lo, c2hi);
+                block_minmax(wave_min_i(near ? max(c2q - kJoinNb, 0) : INT_MAX),
+                             wave_max_i(near ? min(c2q + kJoinNb, (int)mask2) : -1), c2lo, c2hi);
                 if (c2lo > c2hi) continue;
                 const uint32_t rk = lbits | ((uint32_t)c1p << cb2);
                 c0 = wave_lower_bound(gkey, pbeg, pend, rk | (uint32_t)c2lo);

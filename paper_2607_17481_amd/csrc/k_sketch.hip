@@ -660,8 +660,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 }
 
 // SimHash keys, probe order and bucket sort key of every non-constant
-// window, from its stored record.  Blocks are laid out per length
-// (blk_base), so the length's projections sit in LDS for all threads.
+// window of an anchor length (Sec. 3.3: only they are indexed), from its
+// stored record.  Blocks are laid out per anchor length (blk_base), so the
+// length's projections sit in LDS for all threads.
 namespace {
 
 // The FP32 copy f of a window's stored features (zeros when !valid), with
@@ -896,8 +897,9 @@ __global__ __launch_bounds__(kBlock) void k_keys(Req q, const float *__restrict_
         if (h < L.probes) order |= (uint64_t)(top[h] & 31u) << (5 * h);
     q.keyw[kk] = (uint64_t)sig | (order << 24);
     const uint32_t prefix = L.depth ? sig >> (q.B - L.depth) : 0u;
-    q.skey[kk] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
-    q.sval[kk] = (uint32_t)kk;
+    // the sort entries of the anchor windows only, compacted
+    q.skey[L.abase + j] = ((uint32_t)l << q.key_shift) | (prefix << (q.key_shift - L.depth));
+    q.sval[L.abase + j] = (uint32_t)kk;
 }
 
 // First slot of every bucket from the sorted keys: between two consecutive

@@ -39,7 +39,7 @@ struct LenInfo {
     int64_t bucket_base;  // first bucket of this length
     int64_t n_index;      // non-constant windows (entries of the directory)
     int64_t tile_base;    // first sketch tile of this length
-    int64_t blk_base;     // first block of this length in k_keys
+    int64_t blk_base;     // first block of this length in k_keys (anchors own blocks)
     // anchor lengths (Sec. 3.3): the one pass probes only these.  pblk_base
     // is non-decreasing over the lengths: an anchor owns probe blocks
     // [pblk_base, pblk_base + ceil(n_index / 64)), a non-anchor none.
@@ -50,6 +50,10 @@ struct LenInfo {
     int32_t pad_;
     int64_t pblk_base;    // first probe block of this length
     int64_t hblk_base;    // first hint block of this length
+    // Keys and buckets exist at the anchor lengths only (nothing else reads
+    // them): a non-anchor has depth 0 and no k_keys blocks, and an anchor's
+    // sort entries sit at [abase, abase + n_index) of the anchor windows
+    int64_t abase;        // first slot of this length among the anchor windows
 };
 
 // Everything a kernel needs to know about one request.
@@ -140,6 +144,8 @@ __device__ __forceinline__ int find_len_k(const LenInfo *len, int L, int64_t k) 
 constexpr int kJoinTile = 32;             // windows per threshold-join tile
 constexpr int kJoinBlock = 4;             // join tiles per block (they share candidate tiles)
 constexpr int kJoinDirs = 3;              // principal directions per length in the join
+constexpr int kJoinNb = 1;                // join grid cells are 1/kJoinNb of the radius wide; a
+                                          // pair within it lies at most kJoinNb cells apart
 
 // Per length, one round of the threshold join (k_join.hip).
 struct GridLen {

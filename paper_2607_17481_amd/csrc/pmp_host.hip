@@ -305,7 +305,7 @@ struct Plan {
     int L = 0;
     std::vector<int> ms;
     std::vector<LenInfo> len;
-    int64_t cells = 0, ntiles = 0, nbuckets = 0, N = 0, nkblocks = 0;
+    int64_t cells = 0, ntiles = 0, nbuckets = 0, N = 0, Na = 0, nkblocks = 0;
     int64_t nprobe_blocks = 0, nhint_blocks = 0;
     int anchors = 0;
     int max_m = 0, len_bits = 0, key_shift = 0, jkey_shift = 0, max_depth = 0;
@@ -358,19 +358,26 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
             if (p.len[a].anchor) p.len[l].a_hi = a;
     }
     p.nprobe_blocks = p.nhint_blocks = 0;
+    int64_t ab = 0;
     for (int l = 0; l < p.L; ++l) {
         LenInfo &L = p.len[l];
         L.kprime = kprime_of(K, L.m);
         L.n_index = cnt[l];
+        // directories at the anchor lengths only: the one pass probes them
+        // alone, and the lengths between take their hints
         int d = 0;
-        while (d < dcap && L.n_index > (int64_t)alpha << d) ++d;   // Prop. 4 final depth
+        while (L.anchor && d < dcap && L.n_index > (int64_t)alpha << d) ++d;   // Prop. 4 final depth
         L.depth = d;
         int h = d > 0 ? 1 + std::max(0, d - o.d0) : 0;
         h = std::min(h, std::min(d, o.probe_cap));
         L.probes = h;
         L.kbase = kb;
+        L.abase = ab;
         L.blk_base = p.nkblocks;
-        p.nkblocks += (L.n_index + kBlock - 1) / kBlock;
+        if (L.anchor) {
+            p.nkblocks += (L.n_index + kBlock - 1) / kBlock;
+            ab += L.n_index;
+        }
         L.pblk_base = p.nprobe_blocks;
         L.hblk_base = p.nhint_blocks;
         if (L.anchor)
@@ -383,6 +390,7 @@ static void plan_index(Plan &p, const std::vector<int64_t> &cnt, const Opt &o, i
         p.max_depth = std::max(p.max_depth, d);
     }
     p.N = kb;
+    p.Na = ab;
     p.nbuckets = bb;
     p.key_shift = p.max_depth;
     p.jkey_shift = 32 - p.len_bits - 1;
@@ -941,16 +949,19 @@ static int run_pipeline(Run &R, Arena &ar) {
                            b.bl, s);
     }
     tm.mark(11, s);
+    // the debug copy of the key words shows all ones where no key is made
+    // (the lengths between anchors)
+    if (R.dbg && R.dbg->keys) launch_fill_u64(b.keyw, N, ~0ull, s);
     launch_keys(o.precision, q, p.nkblocks, s);
     tm.mark(2, s);
-    if (radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, N, 0, p.key_shift + p.len_bits,
+    if (radix_sort_pairs(b.skey, b.sval, b.skey2, b.sval2, p.Na, 0, p.key_shift + p.len_bits,
                          b.sort_tmp, s, false)) {
         // an odd number of passes leaves the sorted pairs in the scratch pair
         q.skey = b.skey2;
         q.sval = b.sval2;
         q.perm = b.sval2;
     }
-    launch_bucket_bounds(q, N, p.nbuckets, b.bstart, s);
+    launch_bucket_bounds(q, p.Na, p.nbuckets, b.bstart, s);
     launch_hot_buckets(b.bstart, p.nbuckets, q.budget_R, &b.counters[C_HOT], s);
     launch_fill_u32(b.hint, N, kNone, s);
     tm.mark(3, s);
@@ -1041,9 +1052,10 @@ static int run_pipeline(Run &R, Arena &ar) {
                 const double Tr = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9);
                 Rl[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * epmax;
                 Rf[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * efmax;
-                if (p.len[l].n_index > 0 && Rf[l] * (double)(1u << cb) < 2.0 * (nmax * 1.001 + 1e-9))
+                const double cw = Rf[l] / kJoinNb;           // the cell width the radius asks for
+                if (p.len[l].n_index > 0 && cw * (double)(1u << cb) < 2.0 * (nmax * 1.001 + 1e-9))
                     two_d = false;
-                if (p.len[l].n_index > 0 && Rf[l] * (double)(1u << cb3d) < 2.0 * (nmax * 1.001 + 1e-9))
+                if (p.len[l].n_index > 0 && cw * (double)(1u << cb3d) < 2.0 * (nmax * 1.001 + 1e-9))
                     three_d = false;
             }
             const int cb1 = three_d ? cb3d : two_d ? cb : cb_fine;
@@ -1055,7 +1067,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                 GridLen &G = gl[l];
                 G.qlo = -(nmax * 1.001 + 1e-9);
                 // each coordinate's cells span [qlo, -qlo] in 2^bits cells at
-                // least as wide as the radius
+                // least 1/kJoinNb of the radius wide
                 const double hmin = 2.0 * -G.qlo / (double)(1u << cb1) * (1.0 + 1e-9);
                 const double hmin2 = 2.0 * -G.qlo / (double)(1u << std::max(cb2, 1)) * (1.0 + 1e-9);
                 if (std::isinf(Rl[l])) {
@@ -1064,10 +1076,11 @@ static int run_pipeline(Run &R, Arena &ar) {
                 } else {
                     G.R2 = Rl[l] * Rl[l] * (1.0 + 1e-9);
                     // coordinates are computed in FP64 from floats: 1e-12 nmax
-                    // covers their rounding
+                    // covers their rounding; cells of 1/kJoinNb of the radius
+                    // put a pair within it at most kJoinNb cells apart
                     const double hr = (Rf[l] * (1.0 + 1e-9) + 1e-12 * nmax) * (1.0 + 1e-9);
-                    G.hinv = 1.0 / std::max(hr, hmin);
-                    G.hinv2 = 1.0 / std::max(hr, hmin2);
+                    G.hinv = 1.0 / std::max(hr / kJoinNb, hmin);
+                    G.hinv2 = 1.0 / std::max(hr / kJoinNb, hmin2);
                 }
                 G.eps_c = 1.6e-5 * nmax;
                 // per-pair test on the stored coordinates (floats, each within
@@ -1222,8 +1235,9 @@ static int run_pipeline(Run &R, Arena &ar) {
             if (N) hipLaunchKernelGGL(k_debug_scatter, dim3(gb), dim3(256), 0, s, b.cell, N, b.keyw,
                                       0, d->keys);
         }
-        if (d->perm && N)
-            hipLaunchKernelGGL(k_debug_perm, dim3(gb), dim3(256), 0, s, q.perm, b.cell, N, d->perm);
+        if (d->perm && p.Na)
+            hipLaunchKernelGGL(k_debug_perm, dim3(gb), dim3(256), 0, s, q.perm, b.cell, p.Na,
+                               d->perm);
         if (d->bucket_start)
             HIPCHK(hipMemcpyAsync(d->bucket_start, b.bstart, (p.nbuckets + 1) * 4,
                                   hipMemcpyDeviceToDevice, s));

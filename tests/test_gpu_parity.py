@@ -173,8 +173,10 @@ def test_moments_features_keys(gpu, ws, oracle, prec):
     cells = sum(len(t) - m + 1 for m in lengths)
     dbg, bufs, host = _debug_arrays(gpu, cells, 51, PRECS[prec], torch)
     seed = 12345
+    # every length an anchor, so every length has keys (only anchor lengths
+    # are indexed, Sec. 3.3)
     res, st = run(gpu, ws, t, 32, 82, 64, debug=dbg, precision=PRECS[prec], seed=seed,
-                  m_step=25, spectral_width=16)
+                  m_step=25, spectral_width=16, anchor_stride=1)
     mu = bufs["mu"].cpu().numpy()
     sig = bufs["sigma"].cpu().numpy()
     F = bufs["features"].cpu().numpy().astype(np.float64).reshape(cells, 32)
@@ -243,20 +245,21 @@ def test_projections_match_oracle_generator(gpu, oracle):
 
 def test_buckets_occupancy_and_order(gpu, ws, oracle):
     """a4: depth is the final state of global-depth doubling (Prop. 4), each
-    bucket holds the windows whose key prefix is its index, by start."""
+    bucket holds the windows whose key prefix is its index, by start (every
+    length an anchor, so every length has a directory)."""
     import torch
     t = synth.wafer_like(30000, seed=5, copies=4)
     lengths = list(range(50, 60))
     cells = sum(len(t) - m + 1 for m in lengths)
     dbg, bufs, host = _debug_arrays(gpu, cells, len(lengths), 0, torch)
-    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg)       # sizes from the first call
+    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg, anchor_stride=1)   # sizes from the first call
     N = int(host["indexed"].sum())
     nb = int(sum(1 << int(d) for d in host["depth"])) + 1
     perm = torch.empty(N, dtype=torch.int32, device="cuda")
     bst = torch.empty(nb, dtype=torch.int32, device="cuda")
     dbg.perm = perm.data_ptr()
     dbg.bucket_start = bst.data_ptr()
-    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg)
+    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg, anchor_stride=1)
     perm = perm.cpu().numpy().view(np.uint32).astype(np.int64)
     bst = bst.cpu().numpy().view(np.uint32).astype(np.int64)
     keys = bufs["keys"].cpu().numpy().view(np.uint64)
@@ -286,6 +289,53 @@ def test_buckets_occupancy_and_order(gpu, ws, oracle):
         bb += 1 << d
         cb += W
     assert bst[bb] == slot == N
+
+
+
+def test_directories_at_anchor_lengths_only(gpu, ws, oracle):
+    """Sec. 3.3: only anchor lengths are indexed.  With stride 4 over 10
+    lengths (anchors 0, 4, 8, 9) the anchors get the Prop. 4 depth and keys,
+    the lengths between get depth 0, no keys (all ones) and empty buckets,
+    and the bucket order lists exactly the anchors' windows."""
+    import torch
+    t = synth.wafer_like(30000, seed=5, copies=4)
+    lengths = list(range(50, 60))
+    anchors = {0, 4, 8, 9}
+    cells = sum(len(t) - m + 1 for m in lengths)
+    dbg, bufs, host = _debug_arrays(gpu, cells, len(lengths), 0, torch)
+    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg, anchor_stride=4)
+    Na = int(sum(host["indexed"][li] for li in anchors))
+    nb = int(sum(1 << int(d) for d in host["depth"])) + 1
+    perm = torch.empty(max(Na, 1), dtype=torch.int32, device="cuda")
+    bst = torch.empty(nb, dtype=torch.int32, device="cuda")
+    dbg.perm = perm.data_ptr()
+    dbg.bucket_start = bst.data_ptr()
+    res, st = run(gpu, ws, t, 50, 59, 50, debug=dbg, anchor_stride=4)
+    perm = perm.cpu().numpy().view(np.uint32).astype(np.int64)[:Na]
+    bst = bst.cpu().numpy().view(np.uint32).astype(np.int64)
+    keys = bufs["keys"].cpu().numpy().view(np.uint64)
+    alpha = 16
+    cb = bb = slot = 0
+    listed = []
+    for li, m in enumerate(lengths):
+        W = len(t) - m + 1
+        Nm = int(host["indexed"][li])
+        d = int(host["depth"][li])
+        _, _, ocst = oracle.window_stats(t, m)
+        if li in anchors:
+            assert Nm <= alpha << d and (d == 0 or Nm > alpha << (d - 1))
+            assert np.all(keys[cb:cb + W][~ocst] != np.uint64(0xFFFFFFFFFFFFFFFF))
+            listed.append(cb + np.nonzero(~ocst)[0])
+            assert bst[bb] == slot
+            slot += Nm
+        else:
+            assert d == 0
+            assert np.all(keys[cb:cb + W] == np.uint64(0xFFFFFFFFFFFFFFFF))
+            assert bst[bb] == bst[bb + 1] == slot          # one empty bucket
+        bb += 1 << d
+        cb += W
+    assert bst[bb] == slot == Na
+    assert np.array_equal(np.sort(perm), np.sort(np.concatenate(listed)))
 
 
 # ------------------------------------------------ invariances, determinism
