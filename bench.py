@@ -142,11 +142,16 @@ def algorithmic_bytes(n, lengths, st, fs):
         rd += 12 * (w + -(-w // TILE_W) * (m - 1))   # samples + change-point prefix
     nx = st["indexed_cells"]
     cells = sum(n - m + 1 for m in lengths)
-    # the sketch kernel: the samples and change-point counts above, the
-    # cell -> indexed position map (4 per cell, kept when lengths between
-    # anchors exist), and per indexed window its cell, mu, 1/sigma, P and
-    # record
-    sketch = rd + (4 * cells if st["anchors"] < len(lengths) else 0) + nx * (4 + 8 + 8 + 8 + REC * fs)
+    # the sketch kernel's first pass: the samples and change-point counts
+    # above, the cell -> indexed position map (4 per cell, kept when lengths
+    # between anchors exist), per indexed window its cell, mu, 1/sigma and P,
+    # and the records of the anchor lengths' windows (the other lengths get
+    # theirs later, and only where the emit stage and the certificate can
+    # read them)
+    na = st.get("probe_queries", nx)
+    between = st["anchors"] < len(lengths)
+    sketch = (rd + (4 * cells if between else 0) + nx * (4 + 8 + 8 + 8)
+              + (na if between else nx) * REC * fs)
     # the keys kernel, at the anchor lengths' indexed windows (the only ones
     # indexed), reads the record back and writes the key word (8) and the
     # sort key and value (4 + 4)

@@ -703,12 +703,14 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kB
 
 size_t join_cov_doubles(int L) { return (size_t)L * (1 + 32 + 32 * 32); }
 
-void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s) {
+void launch_join_dirs(int precision, const Req &q, int nlen, double *cov, double *udir,
+                      hipStream_t s) {
+    if (nlen <= 0) return;
     if (precision == 0)
-        hipLaunchKernelGGL(k_join_cov<double>, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, cov);
+        hipLaunchKernelGGL(k_join_cov<double>, dim3((unsigned)nlen), dim3(kBlock), 0, s, q, cov);
     else
-        hipLaunchKernelGGL(k_join_cov<float>, dim3((unsigned)q.L), dim3(kBlock), 0, s, q, cov);
-    hipLaunchKernelGGL(k_pca, dim3((unsigned)q.L), dim3(kWave), 0, s, cov, q.L, udir);
+        hipLaunchKernelGGL(k_join_cov<float>, dim3((unsigned)nlen), dim3(kBlock), 0, s, q, cov);
+    hipLaunchKernelGGL(k_pca, dim3((unsigned)nlen), dim3(kWave), 0, s, cov, nlen, udir);
 }
 
 void launch_grid_keys(const Req &q, const GridLen *gl, int64_t N, int cb1, int cb2, int cb3,

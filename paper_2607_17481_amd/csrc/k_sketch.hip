@@ -284,12 +284,13 @@ __device__ __forceinline__ void tile_positions_and_moments(
 template <typename FT>
 __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__restrict__ E,
                                                       const uint32_t *__restrict__ tile_off,
-                                                      int st_len) {
+                                                      int st_len, int mode) {
     extern __shared__ double dyn[];
     __shared__ SketchSmem sm;
     const int64_t tile = blockIdx.x;
     const int l = find_tile_len(q.len, q.L, tile);
     const LenInfo L = q.len[l];
+    if (mode == kSketchBetween && L.anchor) return;       // done by the first pass
     const int m = L.m;
     const int kp = L.kprime;
     const int64_t i0 = (tile - L.tile_base) * kTileW;
@@ -307,6 +308,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_sketch(Req q, const uint32_t *__r
         stage[x / (kFD - 2 * kp)][2 * kp + x % (kFD - 2 * kp)] = 0.0;
 
     tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, sm.kpos, sm.widx, sm.wsum);
+    if (mode == kSketchAnchors && !L.anchor) return;      // records later, if needed
     // ---- sliding DFT in FP64: thread (segment g, bin b)
     const int b = tid & 15;
     const int g = tid >> 4;
@@ -495,7 +497,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                         const int64_t *__restrict__ bbase,
                                                         const uint16_t *__restrict__ bh,
                                                         const uint16_t *__restrict__ bm,
-                                                        const uint16_t *__restrict__ bl) {
+                                                        const uint16_t *__restrict__ bl, int mode) {
     extern __shared__ double dyn[];
     __shared__ int32_t kpos[kTileW];
     __shared__ uint16_t widx[kTileW];
@@ -505,6 +507,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t tile = blockIdx.x;
     const int l = find_tile_len(q.len, q.L, tile);
     const LenInfo L = q.len[l];
+    if (mode == kSketchBetween && L.anchor) return;       // done by the first pass
     const int m = L.m;
     const int mp = (m + 15) & ~15;
     const int64_t i0 = (tile - L.tile_base) * kTileW;
@@ -517,6 +520,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (tid == 0) emax_s = 0;
     load_tile_samples(q.t, i0, nw + m - 1, nw + mp + kMBlk, st);
     tile_positions_and_moments(q, L, i0, nw, tile, st, E, tile_off, kpos, widx, wsum, smu, sis);
+    if (mode == kSketchAnchors && !L.anchor) return;      // records later, if needed
 
     const uint4 *Bh = (const uint4 *)(bh + bbase[l]);
     const uint4 *Bm = (const uint4 *)(bm + bbase[l]);
@@ -937,7 +941,8 @@ void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t nt
 }
 
 void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
-                   int64_t ntiles, int max_m, hipStream_t s) {
+                   int64_t ntiles, int max_m, int mode, hipStream_t s) {
+    if (ntiles <= 0) return;
     // samples (1024 + m - 1 doubles, rounded up to an even count so the
     // staging rows that follow are 16-byte aligned), then the staging rows,
     // sized for the longest window of the request
@@ -947,7 +952,7 @@ void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_
     // (k_sketch_mfma)
     (void)precision;
     hipLaunchKernelGGL((k_sketch<double>), dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                       tile_off, st_len);
+                       tile_off, st_len, mode);
 }
 
 int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base) {
@@ -966,14 +971,15 @@ void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, 
 
 void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                         int64_t ntiles, int max_m, const int64_t *bbase, const uint16_t *bh,
-                        const uint16_t *bm, const uint16_t *bl, hipStream_t s) {
+                        const uint16_t *bm, const uint16_t *bl, int mode, hipStream_t s) {
+    if (ntiles <= 0) return;
     // samples of the tile, padded with zeros for the last block's reads
     const size_t dyn = (size_t)(kTileW + ((max_m + 15) & ~15) + kMBlk) * sizeof(double);
     // both precision forms take FP32-grade features (form 2 differs in its
     // keys only)
     (void)precision;
     hipLaunchKernelGGL(k_sketch_mfma, dim3((unsigned)ntiles), dim3(kBlock), dyn, s, q, E,
-                       tile_off, bbase, bh, bm, bl);
+                       tile_off, bbase, bh, bm, bl, mode);
 }
 
 void launch_join_ops(int precision, const Req &q, int64_t k0, int64_t k1, hipStream_t s) {

@@ -537,8 +537,15 @@ int radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int
 void launch_changepoints(const double *t, int64_t n, uint32_t *flag, int *bad, hipStream_t s);
 void launch_tile_counts(const LenInfo *len, int L, const uint32_t *E, int64_t ntiles,
                         uint32_t *tile_cnt, hipStream_t s);
+// Which tiles of [0, ntiles) the sketch gives records: every length
+// (kSketchAll), the anchor lengths only, the moments and positions of every
+// tile still written (kSketchAnchors), or the lengths between anchors, whose
+// moments and positions a kSketchAnchors pass already wrote (kSketchBetween;
+// it re-writes them with the same values and resets their cells to +inf, so
+// it runs before anything lowers a cell of those lengths)
+enum { kSketchAll = 0, kSketchAnchors = 1, kSketchBetween = 2 };
 void launch_sketch(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
-                   int64_t ntiles, int max_m, hipStream_t s);
+                   int64_t ntiles, int max_m, int mode, hipStream_t s);
 void launch_keys(int precision, const Req &q, int64_t nblocks, hipStream_t s);
 void launch_join_ops(int precision, const Req &q, int64_t k0, int64_t k1, hipStream_t s);
 int64_t basis_elems(const LenInfo *len_host, int L, std::vector<int64_t> &base);
@@ -546,7 +553,7 @@ void launch_basis(const LenInfo *len, int L, const int64_t *base, uint16_t *bh, 
                   uint16_t *bl, int max_m, hipStream_t s);
 void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const uint32_t *tile_off,
                         int64_t ntiles, int max_m, const int64_t *bbase, const uint16_t *bh,
-                        const uint16_t *bm, const uint16_t *bl, hipStream_t s);
+                        const uint16_t *bm, const uint16_t *bl, int mode, hipStream_t s);
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 // (k_probe.hip)
@@ -585,7 +592,10 @@ void launch_select(const uint64_t *P, int64_t n, int64_t need, SelState *st,
 // (k_join.hip)
 size_t join_cov_doubles(int L);
 // principal directions: covariance of a sample, then power iteration (GPU)
-void launch_join_dirs(int precision, const Req &q, double *cov, double *udir, hipStream_t s);
+// principal directions of the lengths [0, nlen) (the lengths whose records
+// exist)
+void launch_join_dirs(int precision, const Req &q, int nlen, double *cov, double *udir,
+                      hipStream_t s);
 // grid keys over cb1 (and cb2, cb3 when nonzero) bits of the principal
 // coordinates, of the first N indexed windows; queries are the cells not at 0
 // with (length, start) <= (l_lim, i_lim)

@@ -671,8 +671,22 @@ static int run_sieve(const Plan &p, Bufs &b, const Req &q, const Opt &o, hipStre
 // the top-k, so only those lengths get hints, and no completion runs (it
 // cannot lower a 0).  `selected`: `acc` holds the selection of the final upper
 // profile (otherwise the caller selects); `rounds`: completion rounds run.
+// The sketch of the tiles [0, ntiles) in the request's form (mode: which
+// tiles get records, kSketch*).
+static void launch_records(const Plan &p, Bufs &b, const Req &q, const Opt &o, int64_t ntiles,
+                           int mode, hipStream_t s) {
+    if (o.precision == 0)
+        launch_sketch(o.precision, q, b.E, b.tile_off, ntiles, p.max_m, mode, s);
+    else
+        launch_sketch_mfma(o.precision, q, b.E, b.tile_off, ntiles, p.max_m, b.bbase, b.bh, b.bm,
+                           b.bl, mode, s);
+}
+
+// rec_lim: with `lazy` (the first pass gave records to the anchor lengths
+// only), the last length whose records exist when this returns
 static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipStream_t s,
-                      Timer &tm, std::vector<Cand> &acc, bool &selected, int &rounds) {
+                      Timer &tm, std::vector<Cand> &acc, bool &selected, int &rounds, bool lazy,
+                      int &rec_lim) {
     rounds = 0;
     selected = false;
     tm.mark(9, s);
@@ -700,6 +714,16 @@ static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipSt
         selected = true;
     }
     const bool zero_kth = acc.size() == (size_t)k && acc.back().d == 0.0;
+    if (lazy) {
+        // the records of the lengths between anchors that the steps below
+        // can read: with a k-th value of 0 those up to the k-th cell's length
+        // (the hints stop before it, and the certificate's queries and
+        // candidates at it, since that key can only move earlier); otherwise
+        // every length.  Nothing has lowered a cell of these lengths yet.
+        rec_lim = zero_kth ? acc.back().l : p.L - 1;
+        const int64_t nt = rec_lim + 1 < p.L ? p.len[rec_lim + 1].tile_base : p.ntiles;
+        launch_records(p, b, q, o, nt, kSketchBetween, s);
+    }
     // hint blocks follow the lengths' order: those of the lengths before the
     // k-th cell's come first
     const int64_t hint_blocks = zero_kth ? p.len[acc.back().l].hblk_base : p.nhint_blocks;
@@ -938,16 +962,19 @@ static int run_pipeline(Run &R, Arena &ar) {
     std::vector<int64_t> bbase;             // lives until the call ends (async copy)
     basis_elems(p.len.data(), p.L, bbase);
     tm.mark(1, s);
-    if (o.precision == 0) {
-        launch_sketch(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, s);
-    } else {
+    // with anchors the first pass gives records to the anchor lengths only:
+    // the probe reads nothing else, and the emit stage adds those of the
+    // other lengths its later steps can reach (all of them unless the k-th
+    // value is 0); a debug copy of the features asks for every record here
+    const bool lazy = o.stride > 1 && !(R.dbg && R.dbg->features);
+    int rec_lim = p.L - 1;
+    if (o.precision != 0) {
         // precision forms: the projection on the matrix cores
         HIPCHK(hipMemcpyAsync(b.bbase, bbase.data(), (p.L + 1) * sizeof(int64_t),
                               hipMemcpyHostToDevice, s));
         launch_basis(b.len, p.L, b.bbase, b.bh, b.bm, b.bl, p.max_m, s);
-        launch_sketch_mfma(o.precision, q, b.E, b.tile_off, p.ntiles, p.max_m, b.bbase, b.bh, b.bm,
-                           b.bl, s);
     }
+    launch_records(p, b, q, o, p.ntiles, lazy ? kSketchAnchors : kSketchAll, s);
     tm.mark(11, s);
     // the debug copy of the key words shows all ones where no key is made
     // (the lengths between anchors)
@@ -986,12 +1013,16 @@ static int run_pipeline(Run &R, Arena &ar) {
     std::vector<Cand> acc;
     int crounds = 0;
     bool selected = false;
-    int rc = emit_stage(p, b, q, o, R.k, s, tm, acc, selected, crounds);
+    int rc = emit_stage(p, b, q, o, R.k, s, tm, acc, selected, crounds, lazy, rec_lim);
     if (rc) return rc;
     tm.mark(8, s);
+    // the largest feature errors again, with the records the emit stage added
+    if (lazy) HIPCHK(hipMemcpyAsync(emax.data(), b.emax, p.L * sizeof(float), hipMemcpyDeviceToHost, s));
     if (!selected) {
         rc = select_topk(p, b, R.k, s, acc);
         if (rc) return rc;
+    } else if (lazy) {
+        HIPCHK(hipStreamSynchronize(s));
     }
     if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
     int rounds = 0;
@@ -1052,11 +1083,11 @@ static int run_pipeline(Run &R, Arena &ar) {
                 const double Tr = Teff * std::sqrt(m / 2.0) * (1.0 + 1e-9);
                 Rl[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * epmax;
                 Rf[l] = std::isinf(Teff) ? INFINITY : Tr + 2.0 * efmax;
+                // (the lengths this round's windows belong to)
                 const double cw = Rf[l] / kJoinNb;           // the cell width the radius asks for
-                if (p.len[l].n_index > 0 && cw * (double)(1u << cb) < 2.0 * (nmax * 1.001 + 1e-9))
-                    two_d = false;
-                if (p.len[l].n_index > 0 && cw * (double)(1u << cb3d) < 2.0 * (nmax * 1.001 + 1e-9))
-                    three_d = false;
+                const bool used = p.len[l].n_index > 0 && l <= l_lim;
+                if (used && cw * (double)(1u << cb) < 2.0 * (nmax * 1.001 + 1e-9)) two_d = false;
+                if (used && cw * (double)(1u << cb3d) < 2.0 * (nmax * 1.001 + 1e-9)) three_d = false;
             }
             const int cb1 = three_d ? cb3d : two_d ? cb : cb_fine;
             const int cb2 = three_d ? cb3d : two_d ? cb : 0;
@@ -1098,7 +1129,7 @@ static int run_pipeline(Run &R, Arena &ar) {
                 gl[l_lim].blk_base + (p.len[l_lim].n_index + win_per_blk - 1) / win_per_blk;
             // the join's operands, for the windows this round queries that
             // have none yet (the principal directions first, once)
-            if (nq_ops == 0 && Nq > 0) launch_join_dirs(o.precision, q, b.cov, b.udir, s);
+            if (nq_ops == 0 && Nq > 0) launch_join_dirs(o.precision, q, rec_lim + 1, b.cov, b.udir, s);
             launch_join_ops(o.precision, q, nq_ops, Nq, s);
             nq_ops = std::max(nq_ops, Nq);
             launch_grid_keys(q, b.gl, Nq, cb1, cb2, cb3, l_lim, i_lim, b.jk, b.jv, b.qf, b.gp, s);
