@@ -286,6 +286,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t *__restrict__ p, i
         p[i] = v;
 }
 
+// The number of the n values of P that are 0 (the FP64 bits of +0),
+// added to *out.
+__global__ __launch_bounds__(kBlock) void k_count_zero(const uint64_t *__restrict__ P, int64_t n,
+                                                       unsigned long long *__restrict__ out) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        c += P[i] == 0ull;
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ p, int64_t n,
                                                      uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -339,6 +351,11 @@ void launch_rows(const Req &q, const RowReq *rr, int nrows, int64_t maxN,
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,
                        hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_gather_u32, dim3(nblk(n)), dim3(kBlock), 0, s, src, idx, n, out);
+}
+
+void launch_count_zero(const uint64_t *P, int64_t n, unsigned long long *out, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_count_zero, dim3(gridcap(n, 1024)), dim3(kBlock), 0, s, P, n, out);
 }
 
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {

@@ -59,18 +59,20 @@ struct QwinA {
 // candidate chain's latency than three without spills.
 template <typename FT>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4)))
-void k_probe(Req q, const uint32_t *__restrict__ bstart, int qcap) {
-    // the anchor length of this block: the last length whose first probe
-    // block is at or below it (uniform)
+void k_probe(Req q, const uint32_t *__restrict__ bstart, int qcap, int64_t blk0) {
+    // the anchor length of this block (blocks [blk0, blk0 + gridDim.x) of
+    // the probe): the last length whose first probe block is at or below it
+    // (uniform)
+    const int64_t gb = blk0 + (int64_t)blockIdx.x;
     int lb = 0;
     {
         int hi = q.L - 1;
         while (lb < hi) {
             const int mid = (lb + hi + 1) >> 1;
-            if (q.len[mid].pblk_base <= (int64_t)blockIdx.x) lb = mid; else hi = mid - 1;
+            if (q.len[mid].pblk_base <= gb) lb = mid; else hi = mid - 1;
         }
     }
-    const int64_t k_first = q.len[lb].kbase + ((int64_t)blockIdx.x - q.len[lb].pblk_base) * kWave;
+    const int64_t k_first = q.len[lb].kbase + (gb - q.len[lb].pblk_base) * kWave;
     const int64_t k = k_first + threadIdx.x;
     uint32_t n_cand = 0, n_ver = 0;
 
@@ -286,16 +288,16 @@ __global__ __launch_bounds__(kBlock) void k_hot_buckets(const uint32_t *__restri
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t nblocks,
-                  int max_m, hipStream_t s) {
+void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t blk0,
+                  int64_t nblocks, int max_m, hipStream_t s) {
     if (nblocks <= 0) return;
     const dim3 grid((unsigned)nblocks);
     const int qcap = kQwinExtra + max_m;
     const size_t lds = (size_t)qcap * sizeof(double);
     if (precision == 0)
-        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), lds, s, q, bstart, qcap);
+        hipLaunchKernelGGL(k_probe<double>, grid, dim3(kWave), lds, s, q, bstart, qcap, blk0);
     else
-        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), lds, s, q, bstart, qcap);
+        hipLaunchKernelGGL(k_probe<float>, grid, dim3(kWave), lds, s, q, bstart, qcap, blk0);
 }
 
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,

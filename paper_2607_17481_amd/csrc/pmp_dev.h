@@ -557,9 +557,10 @@ void launch_sketch_mfma(int precision, const Req &q, const uint32_t *E, const ui
 void launch_bucket_bounds(const Req &q, int64_t N, int64_t nbuckets, uint32_t *bstart,
                           hipStream_t s);
 // (k_probe.hip)
-// one wavefront per 64 indexed windows of each anchor length (LenInfo.pblk_base)
-void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t nblocks,
-                  int max_m, hipStream_t s);
+// one wavefront per 64 indexed windows of each anchor length (LenInfo.pblk_base):
+// the probe blocks [blk0, blk0 + nblocks)
+void launch_probe(int precision, const Req &q, const uint32_t *bstart, int64_t blk0,
+                  int64_t nblocks, int max_m, hipStream_t s);
 void launch_hot_buckets(const uint32_t *bstart, int64_t nb, int R, unsigned long long *cnt,
                         hipStream_t s);
 // (k_complete.hip): the emit stage
@@ -629,6 +630,8 @@ void launch_stream_merge(const StreamDev &S, const SMerge *mg, int nmerge, int64
                          hipStream_t s);
 void launch_iota_u32(uint32_t *p, int64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+// *out += the number of zeros among P[0 .. n)
+void launch_count_zero(const uint64_t *P, int64_t n, unsigned long long *out, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_gather_u32(const uint32_t *src, const uint32_t *idx, int64_t n, uint32_t *out,
                        hipStream_t s);

@@ -688,7 +688,6 @@ static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipSt
                       Timer &tm, std::vector<Cand> &acc, bool &selected, int &rounds, bool lazy,
                       int &rec_lim) {
     rounds = 0;
-    selected = false;
     tm.mark(9, s);
     tm.mark(10, s);
     if (p.N == 0) return PMP_OK;
@@ -708,7 +707,7 @@ static int emit_stage(const Plan &p, Bufs &b, Req &q, const Opt &o, int k, hipSt
         tm.mark(10, s);
         return PMP_OK;
     }
-    {
+    if (!selected || o.sieve_w > 0) {
         const int rc = select_topk(p, b, k, s, acc);
         if (rc) return rc;
         selected = true;
@@ -993,7 +992,39 @@ static int run_pipeline(Run &R, Arena &ar) {
     launch_fill_u32(b.hint, N, kNone, s);
     tm.mark(3, s);
     tm.mark(4, s);
-    launch_probe(o.precision, q, b.bstart, p.nprobe_blocks, p.max_m, s);
+    // the selection after the first anchor's probe, when it settled the top-k
+    std::vector<Cand> acc0;
+    bool have_acc0 = false;
+    // The first anchor length alone first.  When its cells already give k
+    // accepted cells at 0, every cell of a longer length comes after the k-th
+    // in the (P, m, i) order and can change nothing: the other anchors'
+    // probes are skipped (the certificate stops at that length too).
+    {
+        int a1 = -1;                                   // the second anchor
+        for (int l = 1; l < p.L && a1 < 0; ++l)
+            if (p.len[l].anchor) a1 = l;
+        const int64_t first = a1 < 0 ? p.nprobe_blocks : p.len[a1].pblk_base;
+        launch_probe(o.precision, q, b.bstart, 0, first, p.max_m, s);
+        bool rest = first < p.nprobe_blocks;
+        if (rest && o.certify) {
+            // fewer than k zeros at the first length (counted on the device,
+            // in the join's pair counter, free until the certificate) cannot
+            // give k accepted ones; otherwise the selection decides
+            unsigned long long zeros = 0;
+            launch_fill_u64((uint64_t *)b.jcount, 1, 0ull, s);
+            launch_count_zero(b.P + p.len[0].kbase, p.len[0].n_index, b.jcount, s);
+            HIPCHK(hipMemcpyAsync(&zeros, b.jcount, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (zeros >= (unsigned long long)R.k) {
+                const int rc = select_topk(p, b, R.k, s, acc0);
+                if (rc) return rc;
+                rest = !(acc0.size() == (size_t)R.k && acc0.back().d == 0.0);
+                have_acc0 = !rest;
+            }
+        }
+        if (rest)
+            launch_probe(o.precision, q, b.bstart, first, p.nprobe_blocks - first, p.max_m, s);
+    }
     tm.mark(5, s);
     HIPCHK(hipGetLastError());
 
@@ -1013,6 +1044,11 @@ static int run_pipeline(Run &R, Arena &ar) {
     std::vector<Cand> acc;
     int crounds = 0;
     bool selected = false;
+    // (no kernel has changed P since that selection unless the sieve runs)
+    if (have_acc0 && o.sieve_w == 0) {
+        acc = acc0;
+        selected = true;
+    }
     int rc = emit_stage(p, b, q, o, R.k, s, tm, acc, selected, crounds, lazy, rec_lim);
     if (rc) return rc;
     tm.mark(8, s);
@@ -1021,7 +1057,8 @@ static int run_pipeline(Run &R, Arena &ar) {
     if (!selected) {
         rc = select_topk(p, b, R.k, s, acc);
         if (rc) return rc;
-    } else if (lazy) {
+    } else {
+        // the copies of the flag and the feature errors complete here
         HIPCHK(hipStreamSynchronize(s));
     }
     if (bad) return fail(PMP_EINVAL, "series has windows whose standard deviation underflows");
