@@ -161,6 +161,8 @@ def algorithmic_bytes(n, lengths, st, fs):
     # verified pair: the candidate's moments and the two cell updates (the
     # samples of both windows are read from the series, which stays resident
     # in the caches: 8 n bytes in all)
+    # (the anchor windows; an upper figure when the first anchor settled the
+    # top-k and the probe ran that anchor only)
     nq = st.get("probe_queries", nx)
     probe = (nq * (REC * fs + 4 + 4 + 8 + 8 + 8 + 8 + 4)
              + st["pass_candidates"] * (REC * fs + 4 + 4 + 8)

@@ -150,7 +150,9 @@ typedef struct {
     uint64_t join_windows;      /* windows given join operands (the lengths
                                    up to the key bound of the last round)    */
     uint64_t probe_queries;     /* indexed windows of the anchor lengths (the
-                                   probe's queries)                          */
+                                   probe's queries; when the first anchor's
+                                   cells already settle the top-k at 0, the
+                                   probe runs that anchor's only)            */
 } pmp_stats;
 
 /* Exact top-k pan-motifs of a host series.  lengths m_min..m_max (step 1),
